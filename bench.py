@@ -1,0 +1,225 @@
+#!/usr/bin/env python
+"""Interaction-matrix build benchmark on one MI355X.
+
+Workload: the ELT-scale SCAO IM in FP32 - 80x80 subapertures of 6 px on a
+480-px pupil with 28% central obscuration (4632 valid subapertures), a 81x81
+Gaussian-IF DM (5257 actuators inside the pupil, 512^2 IF grid, 5.5 GB stack
+resident in HBM) and a seeded misregistration.  One step = one full IM build
+(geometry plan + streaming pass over every IF) = 5257 IM columns.
+
+Printed JSON line: IM columns/s of the whole step, the streaming kernel's
+achieved algorithmic HBM bandwidth against the 8 TB/s peak (HIP events on the
+launch stream), and the FP64 oracle's rate on a bounded sample of the same
+workload on the host cores.
+
+    python bench.py [--steps K] [--warmup W] [--seed S] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "IM columns/s & % HBM roofline; misreg-fit ms, learned vs Gauss-Newton"
+PEAK_HBM_GBS = 8000.0
+STREAM_SRC = os.path.join(ROOT, "paper_2606_07759_amd", "csrc", "im_build.hip")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "im_stream_elt_traffic.json")
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# ------------------------------------------------------------ algorithmic bytes
+def touched_if_pixels(cfg, A) -> int:
+    """|S|: IF pixels with a non-zero bilinear weight for some sample that the
+    central differences read (the 4-neighbours of every pupil pixel of a valid
+    subaperture).  Depends on the geometry only, not on any kernel."""
+    import numpy as np
+    H, W = cfg.pupil.shape
+    p = cfg.p
+    ns = W // p
+    use = np.zeros((H, W), bool)
+    for k in cfg.valid:
+        v, u = divmod(int(k), ns)
+        use[v * p:(v + 1) * p, u * p:(u + 1) * p] = cfg.pupil[v * p:(v + 1) * p, u * p:(u + 1) * p] > 0
+    Q = np.zeros((H + 2, W + 2), bool)          # haloed sample grid
+    Q[1:-1, 2:] |= use
+    Q[1:-1, :-2] |= use
+    Q[2:, 1:-1] |= use
+    Q[:-2, 1:-1] |= use
+    yy, xx = np.nonzero(Q)
+    x = xx - 1.0
+    y = yy - 1.0
+    xs = A[0, 0] * x + A[0, 1] * y + A[0, 2]
+    ys = A[1, 0] * x + A[1, 1] * y + A[1, 2]
+    i = np.floor(xs).astype(np.int64)
+    j = np.floor(ys).astype(np.int64)
+    a = xs - i
+    c = ys - j
+    Hi = Wi = cfg.grid.grid_n
+    S = np.zeros((Hi + 2, Wi + 2), bool)
+    for di, dj, w in ((0, 0, (1 - a) * (1 - c)), (1, 0, a * (1 - c)), (0, 1, (1 - a) * c), (1, 1, a * c)):
+        nz = w != 0
+        ii = i[nz] + di
+        jj = j[nz] + dj
+        ok = (ii >= 0) & (ii < Wi) & (jj >= 0) & (jj < Hi)
+        S[jj[ok], ii[ok]] = True
+    return int(S.sum())
+
+
+# ----------------------------------------------------------------- CPU baseline
+def _oracle_chunk(args):
+    seed, cols = args
+    import numpy as np
+    import workloads as wl
+    from oracle import geometry as og, im as oim
+    cfg = wl.scao_elt(seed)
+    A, b = og.inverse_from_misreg(cfg.theta, 512, 512, cfg.n_out, cfg.n_out)
+    F = np.stack([wl.if_single(cfg.grid, a) for a in cols])
+    t0 = time.perf_counter()
+    oim.im_build(F, A, b, cfg.pupil, cfg.p, cfg.valid)
+    return time.perf_counter() - t0
+
+
+def cpu_baseline(seed: int, target_s: float):
+    """FP64 oracle on a bounded sample of the same workload, on the host cores.
+
+    Runs before the GPU is touched, in a pool of spawned worker processes."""
+    import concurrent.futures as cf
+    import multiprocessing as mp
+    import numpy as np
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count() or 1
+    workers = max(1, min(16, ncpu))
+    chunk = 4
+    # calibrate on one chunk in-process
+    t1 = _oracle_chunk((seed, list(range(chunk))))
+    per_col = t1 / chunk
+    n_cols = int(max(workers * chunk, min(5257, target_s * workers / per_col)))
+    n_cols = (n_cols + chunk - 1) // chunk * chunk
+    cols = np.linspace(0, 5256, n_cols).astype(int).tolist()
+    jobs = [(seed, cols[i:i + chunk]) for i in range(0, n_cols, chunk)]
+    log(f"cpu baseline: {n_cols} columns on {workers} workers (~{per_col:.3f} s/column/core)")
+    ctx = mp.get_context("spawn")
+    t0 = time.perf_counter()
+    with cf.ProcessPoolExecutor(max_workers=workers, mp_context=ctx) as ex:
+        list(ex.map(_oracle_chunk, jobs))
+    wall = time.perf_counter() - t0
+    return {"value": n_cols / wall, "unit": "IM columns/s", "cores": workers, "kind": "oracle",
+            "sample": f"{n_cols} of 5257 IM columns of the ELT workload (seed {seed}), FP64 "
+                      f"NumPy oracle, {workers} worker processes, {wall:.1f} s wall"}
+
+
+def stored_traffic(n_launch_bytes):
+    """HBM traffic of the streaming kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            rec = json.load(f)
+        with open(STREAM_SRC, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()[:16]
+        if rec.get("kernel_sha") != h:
+            return None
+        return float(rec["bytes_per_launch"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the IM build shards by actuator columns with no "
+              "exchange, so only --gpus 1 is run here", file=sys.stderr)
+        sys.exit(2)
+
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.seed, args.cpu_seconds)
+
+    import numpy as np
+    import torch
+    import paper_2606_07759_amd as synim
+    import workloads as wl
+
+    synim.load()
+    dev = torch.device("cuda:0")
+    cfg = wl.scao_elt(args.seed)
+    n_act, H = cfg.grid.n_act, cfg.n_out
+    log(f"generating {n_act} IFs of {cfg.grid.grid_n}^2 on the device")
+    Fd = wl.if_stack_torch(cfg.grid, dev)
+    A, _ = synim.affine_from_misreg(cfg.theta, 512, 512, H, H)
+    wfs = synim.Wfs.from_numpy(cfg.pupil, cfg.p, cfg.valid, device=dev)
+    ws = torch.empty(synim.im_workspace_bytes(wfs, A, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty((n_act, 2 * cfg.n_valid), dtype=torch.float32, device=dev)
+
+    S = touched_if_pixels(cfg, A)
+    bytes_per_col = 4 * S + 8 * cfg.n_valid
+    launch_bytes = bytes_per_col * n_act
+
+    for _ in range(args.warmup):
+        synim.im_plan(wfs, A, ws=ws)
+        synim.im_apply(Fd, A, wfs, ws, out=out)
+    torch.cuda.synchronize()
+    if synim.plan_status(ws) != 0:
+        raise RuntimeError("plan status non-zero")
+    log(f"warmup done; timing {args.steps} steps")
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        synim.im_plan(wfs, A, ws=ws)
+        ev[k][0].record()
+        synim.im_apply(Fd, A, wfs, ws, out=out)
+        ev[k][1].record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    apply_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
+    achieved = launch_bytes / (apply_ms * 1e-3) / 1e9
+    traffic = stored_traffic(launch_bytes)
+    rec = {
+        "metric": METRIC,
+        "value": n_act / (ms_step * 1e-3),
+        "unit": "IM columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"ELT SCAO IM: 80x80 subap x 6 px, 480-px pupil 28% obscured, "
+                               f"{n_act} Gaussian IFs on 512^2, seed {args.seed}",
+                   "n_act": n_act, "n_valid": cfg.n_valid, "if_grid": 512,
+                   "theta": [float(v) for v in cfg.theta]},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": achieved / PEAK_HBM_GBS, "traffic": traffic},
+        "cpu_baseline": cpu,
+        "detail": {"stream_kernel_ms": apply_ms, "plan_plus_stream_ms": ms_step,
+                   "algorithmic_bytes_per_column": bytes_per_col,
+                   "touched_if_pixels_per_column": S, "algorithmic_bytes_per_launch": launch_bytes},
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * synim.h - C ABI of the MI355X (gfx950) synthetic interaction-matrix library.
+ *
+ * The library forms synthetic Shack-Hartmann interaction-matrix (IM) columns:
+ * every deformable-mirror influence function (IF) is resampled onto the WFS
+ * grid by ONE composite affine map with a single bilinear interpolation
+ * (SynIM paper, Sec. 2.1 "Geometric Mapping and Single-Step Interpolation"),
+ * then turned into per-subaperture x/y slopes by central finite differences
+ * at every pupil pixel and a mean over each subaperture on the exactly aligned
+ * grid (Sec. 2.2 "Slope Computation").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Coordinates   pixel (row y, column x) has its centre at integer (x, y); a
+ *               grid of n pixels has its centre at (n-1)/2.
+ * Inverse map   synim_affine holds p_s = A p_o + b: WFS (output) pixel ->
+ *               IF (source) pixel, x first.  IF samples outside the IF grid
+ *               are zero.
+ * Subapertures  the WFS grid is (n_sub_y*p) x (n_sub_x*p) pixels; subaperture
+ *               (u, v) covers columns u*p..u*p+p-1, rows v*p..v*p+p-1 and has
+ *               row-major id k = v*n_sub_x + u.  valid_idx lists the ids of the
+ *               valid subapertures, strictly ascending; N = n_valid.
+ * Slopes        for valid subaperture k with n_k pupil pixels,
+ *               s_x = sum_{P=1} (phi[y][x+1] - phi[y][x-1]) / (2 n_k), s_y
+ *               likewise; units: phase per WFS pixel.
+ * IM layout     actuator-major: im[a*2N + i] = s_x of valid subaperture i,
+ *               im[a*2N + N + i] = s_y (x block then y block).  This is the
+ *               transpose of the paper's 2N x N_modes matrix.
+ * Memory        every array argument is a DEVICE pointer unless marked
+ *               (host); descriptors (synim_affine, synim_wfs, ...) are host
+ *               structs read during the call.  The caller owns all memory.
+ *               Entry points taking a workspace never allocate; size it
+ *               with the matching *_workspace query.
+ * Streams       work is enqueued on the hipStream_t passed as `stream` (NULL =
+ *               default stream); calls return after enqueueing.  Argument
+ *               errors are reported synchronously; device-side faults surface
+ *               as SYNIM_E_HIP from a later synchronising call.
+ * Threads       all entry points are re-entrant; the autotune cache is guarded.
+ */
+#ifndef SYNIM_H
+#define SYNIM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  SYNIM_OK = 0,
+  SYNIM_E_NULL = -1,          /* a required pointer is NULL                      */
+  SYNIM_E_SHAPE = -2,         /* inconsistent or unsupported sizes               */
+  SYNIM_E_PARAM = -3,         /* invalid parameter value (e.g. magnification 0)  */
+  SYNIM_E_OOB = -4,           /* strict mode: samples fell outside the IF grid   */
+  SYNIM_E_WORKSPACE = -5,     /* workspace missing or too small                  */
+  SYNIM_E_HIP = -6,           /* a HIP runtime call failed                       */
+  SYNIM_E_NOT_CONVERGED = -7, /* Gauss-Newton hit its iteration limit            */
+  SYNIM_E_UNSUPPORTED = -8    /* no kernel variant for this geometry             */
+} synim_status;
+
+/* Human-readable name of a status code (static string). */
+const char* synim_status_str(int status);
+/* Library version, major*10000 + minor*100 + patch. */
+int synim_version(void);
+
+/* Inverse affine map p_s = A p_o + b (see Conventions). */
+typedef struct {
+  double A[2][2];
+  double b[2];
+} synim_affine;
+
+/* Plain misregistration of a DM seen by a WFS (forward map, about the grid
+ * centres c_s, c_o):  p_o = c_o + t + (mag/kappa) R(rot) (p_s - c_s),
+ * R(phi) = [[cos, -sin], [sin, cos]] on (x, y); t = (shift_x, shift_y) in WFS px. */
+typedef struct {
+  double shift_x, shift_y;
+  double rot;   /* radians */
+  double mag;
+} synim_misreg;
+
+/* Composite DM -> WFS geometry (Sec. 2.1: the DM transform, the LGS
+ * perspective at the DM altitude and the WFS transform multiplied into one
+ * matrix).  Forward chain, each part about its grid centre:
+ *   DM placement   v = dm_mag R(dm_rot) u + dm_shift          (DM px)
+ *   LGS footprint  w = (v - footprint) / (kappa * cone_scale)  (WFS px)
+ *   WFS            p_o - c_o = diag(wfs_mag_x, wfs_mag_y) R(wfs_rot) w + wfs_shift
+ * cone_scale = 1 - h/H_LGS; footprint = h*alpha / DM pixel size. */
+typedef struct {
+  double dm_shift_x, dm_shift_y, dm_rot, dm_mag;
+  double cone_scale, footprint_x, footprint_y;
+  double wfs_shift_x, wfs_shift_y, wfs_rot, wfs_mag_x, wfs_mag_y;
+  double kappa;   /* DM pixels per WFS pixel */
+} synim_geometry;
+
+/* Shack-Hartmann WFS description. */
+typedef struct {
+  int32_t n_sub_x, n_sub_y;   /* subapertures per row / column                */
+  int32_t p;                  /* pixels per subaperture side                  */
+  int32_t n_valid;            /* N, number of valid subapertures (>= 1)       */
+  const int32_t* valid_idx;   /* device [N], ascending row-major ids          */
+  const uint8_t* pupil;       /* device [n_sub_y*p][n_sub_x*p], 0/1           */
+} synim_wfs;
+
+/* ---------------------------------------------------------------- geometry */
+
+/* Inverse map of a plain misregistration (Sec. 2.1), and optionally the four
+ * derivative maps d p_s / d theta_j = dA[j].A p_o + dA[j].b for theta =
+ * (shift_x, shift_y, rot, mag).  Grid sizes are those of the IF (in) and WFS
+ * (out) grids; kappa = IF pixels per WFS pixel.
+ * A (host, out) required; dA (host, out, 4 entries) may be NULL.
+ * Errors: SYNIM_E_NULL, SYNIM_E_PARAM (mag or kappa <= 0, sizes < 1). */
+int synim_affine_from_misreg(const synim_misreg* theta, int H_in, int W_in, int H_out, int W_out,
+                             double kappa, synim_affine* A, synim_affine* dA);
+
+/* Inverse map of a composite geometry (Sec. 2.1, LGS cone effect and
+ * off-axis footprint, WFS anamorphosis), composed and inverted in FP64 on the
+ * host.  Errors: SYNIM_E_NULL, SYNIM_E_PARAM (singular chain). */
+int synim_affine_from_geometry(const synim_geometry* g, int H_in, int W_in, int H_out, int W_out,
+                               synim_affine* A);
+
+/* -------------------------------------------------------- standalone steps */
+
+/* Bilinear resampling of n IFs onto the WFS grid with a `halo`-pixel border
+ * (Sec. 2.1 single interpolation):
+ *   out[i][y+halo][x+halo] = bilinear(ifs[i], A (x, y) + b)
+ * for x in [-halo, W_out+halo), y in [-halo, H_out+halo).
+ *   ifs   device float32 [n][H_in][W_in], row-major
+ *   out   device float32 [n][H_out+2*halo][W_out+2*halo]
+ *   oob_count  device int32[1] or NULL: incremented (atomically) by the number
+ *         of output pixels of one IF whose source point lies outside
+ *         [0, W_in-1] x [0, H_in-1]; the caller zeroes it beforehand.
+ * Errors: SYNIM_E_NULL, SYNIM_E_SHAPE (n, sizes < 1, halo < 0 or > 8),
+ *         SYNIM_E_HIP. */
+int synim_affine_warp(const float* ifs, int n, int H_in, int W_in, const synim_affine* A,
+                      int H_out, int W_out, int halo, float* out, int32_t* oob_count, void* stream);
+
+/* Slopes of n haloed phase maps (Sec. 2.2 central differences + subaperture
+ * means).
+ *   phase  device float32 [n][H+2][W+2] with pixel (x, y) at [y+1][x+1],
+ *          H = n_sub_y*p, W = n_sub_x*p
+ *   slopes device float32 [n][2N]
+ * Errors: SYNIM_E_NULL, SYNIM_E_SHAPE, SYNIM_E_HIP. */
+int synim_sa_slopes(const float* phase, int n, const synim_wfs* wfs, float* slopes, void* stream);
+
+/* ------------------------------------------------------------ fused build */
+
+/* Workspace bytes for synim_im_build / synim_im_jacobian / synim_im_vjp on
+ * this WFS and map.  `planes` = 1 for the IM, 5 for IM + 4 Jacobian planes.
+ * Errors: SYNIM_E_NULL, SYNIM_E_SHAPE, SYNIM_E_UNSUPPORTED (map too strongly
+ * magnified for every kernel variant). */
+int synim_im_workspace(const synim_wfs* wfs, const synim_affine* A, int planes, size_t* bytes);
+
+/* Interaction matrix of n_act IFs (Sec. 2.1 + 2.2, fused): for every IF the
+ * composite-map bilinear resampling, the central differences at pupil pixels
+ * and the subaperture means, in one pass over the IF stack.
+ *   ifs  device float32 [n_act][H_in][W_in]
+ *   im   device float32 [n_act][2N] (IM layout above)
+ *   ws   device workspace of at least synim_im_workspace(.., planes=1) bytes
+ * The geometry is folded, per valid subaperture, into one dense weight patch
+ * computed in FP64 on the device; the IF stack is then streamed once.
+ * Errors: SYNIM_E_NULL, SYNIM_E_SHAPE, SYNIM_E_WORKSPACE, SYNIM_E_UNSUPPORTED,
+ *         SYNIM_E_HIP. */
+int synim_im_build(const float* ifs, int n_act, int H_in, int W_in, const synim_affine* A,
+                   const synim_wfs* wfs, float* im, void* ws, size_t ws_bytes, void* stream);
+
+/* IM and its Jacobian with respect to theta_j (j = 0..3) for the derivative
+ * maps dA (from synim_affine_from_misreg):
+ *   d phi / d theta_j = grad bilinear(F, p_s) . (dA[j].A p_o + dA[j].b)
+ * with the floor-cell (right-continuous) bilinear gradient, then the slope
+ * step.  im may be NULL; dim is device float32 [4][n_act][2N].
+ * Workspace: synim_im_workspace(.., planes=5). */
+int synim_im_jacobian(const float* ifs, int n_act, int H_in, int W_in, const synim_affine* A,
+                      const synim_affine* dA, const synim_wfs* wfs, float* im, float* dim,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of the IM with respect to theta:
+ *   grad_theta[j] = sum_{a,r} grad_im[a][r] * dIM/dtheta_j[a][r]
+ * computed without materialising the Jacobian.
+ *   grad_im    device float32 [n_act][2N]
+ *   grad_theta device float64 [4] (overwritten)
+ * Workspace: synim_im_workspace(.., planes=5) + synim_vjp_extra_workspace(). */
+int synim_im_vjp(const float* ifs, int n_act, int H_in, int W_in, const synim_affine* A,
+                 const synim_affine* dA, const synim_wfs* wfs, const float* grad_im,
+                 double* grad_theta, void* ws, size_t ws_bytes, void* stream);
+
+/* --------------------------------------------------- plan / apply split
+ * synim_im_build = synim_im_plan + synim_im_apply(plane 0).  Splitting them
+ * lets a caller fold the geometry once and stream several IF stacks (or time
+ * the streaming kernel alone).  The plan lives in `ws`; apply must be called
+ * with the same wfs, A and `planes` as the plan. */
+
+/* Fold the geometry into per-subaperture weight patches in `ws` (FP64 on the
+ * device).  planes = 1 (IM) or 5 (IM + 4 Jacobian planes, dA required). */
+int synim_im_plan(const synim_wfs* wfs, const synim_affine* A, const synim_affine* dA, int planes,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* Stream n_act IFs through plane `plane` (0 = IM, 1..4 = d/dtheta_j) of a plan
+ * built by synim_im_plan; out is device float32 [n_act][2N]. */
+int synim_im_apply(const float* ifs, int n_act, int H_in, int W_in, const synim_affine* A,
+                   const synim_wfs* wfs, int planes, int plane, float* out, const void* ws,
+                   size_t ws_bytes, void* stream);
+
+/* Device status word of the last plan built in `ws`: bit 0 a weight patch was
+ * too small for the map, bit 1 a tile bounding box overflowed (that tile's
+ * slopes are not written), bit 2 a valid subaperture has no pupil pixel (its
+ * slopes are 0).  0 means the plan is complete.  Copies 4 bytes to host_out
+ * and synchronises `stream`. */
+int synim_plan_status(const void* ws, int* host_out, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SYNIM_H */

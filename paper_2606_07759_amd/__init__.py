@@ -1,0 +1,279 @@
+"""Python binding of the MI355X synthetic interaction-matrix library.
+
+Argument marshalling only: every step of the interaction-matrix path runs in the
+HIP kernels of ``libsynim.so`` (C ABI in ``include/synim.h``).  PyTorch supplies
+device memory and the current stream.  There is no CPU fallback: if the
+library is missing or no GPU is present, the calls raise.
+
+Geometry conventions (pixel centres, inverse map, IM layout) are those of the
+C header.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+from typing import Optional, Sequence, Tuple
+
+import numpy as np
+
+from . import _abi
+
+_LIB: Optional[C.CDLL] = None
+
+
+class SynimError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        self.status = status
+        msg = _LIB.synim_status_str(status).decode() if _LIB is not None else str(status)
+        super().__init__(f"{where}: {msg} ({status})")
+
+
+def load() -> C.CDLL:
+    """Load ``libsynim.so`` (once); raises if it is not built."""
+    global _LIB
+    if _LIB is None:
+        _LIB = _abi.load_library()
+    return _LIB
+
+
+def _check(rc: int, where: str):
+    if rc != 0:
+        raise SynimError(rc, where)
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(device) -> int:
+    torch = _torch()
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _dev_f32(t, name: str):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != torch.float32 or not t.is_contiguous():
+        raise TypeError(f"{name} must be contiguous float32")
+    return t
+
+
+# ------------------------------------------------------------------- geometry
+def _affine_struct(A) -> _abi.SynimAffine:
+    if isinstance(A, _abi.SynimAffine):
+        return A
+    M = np.asarray(A, dtype=np.float64).reshape(2, 3)
+    s = _abi.SynimAffine()
+    for i in range(2):
+        for j in range(2):
+            s.A[i][j] = M[i, j]
+        s.b[i] = M[i, 2]
+    return s
+
+
+def affine_to_array(s: _abi.SynimAffine) -> np.ndarray:
+    return np.array([[s.A[0][0], s.A[0][1], s.b[0]], [s.A[1][0], s.A[1][1], s.b[1]]])
+
+
+def affine_from_misreg(theta: Sequence[float], H_in: int, W_in: int, H_out: int, W_out: int,
+                       kappa: float = 1.0) -> Tuple[np.ndarray, np.ndarray]:
+    """(A [2x3], dA [4x2x3]) of p_s = A[:, :2] p_o + A[:, 2] and its derivative maps."""
+    lib = load()
+    th = _abi.SynimMisreg(*[float(v) for v in theta])
+    A = _abi.SynimAffine()
+    dA = (_abi.SynimAffine * 4)()
+    _check(lib.synim_affine_from_misreg(C.byref(th), H_in, W_in, H_out, W_out, float(kappa),
+                                        C.byref(A), dA), "affine_from_misreg")
+    return affine_to_array(A), np.stack([affine_to_array(dA[j]) for j in range(4)])
+
+
+def affine_from_geometry(g, H_in: int, W_in: int, H_out: int, W_out: int) -> np.ndarray:
+    """Inverse map [2x3] of a composite geometry (fields as ``synim_geometry``)."""
+    lib = load()
+    s = _abi.SynimGeometry(**{n: float(getattr(g, n)) for n, _ in _abi.SynimGeometry._fields_})
+    A = _abi.SynimAffine()
+    _check(lib.synim_affine_from_geometry(C.byref(s), H_in, W_in, H_out, W_out, C.byref(A)),
+           "affine_from_geometry")
+    return affine_to_array(A)
+
+
+# ------------------------------------------------------------------------ WFS
+@dataclass
+class Wfs:
+    """Device-resident Shack-Hartmann WFS description (pupil and valid list)."""
+    n_sub_x: int
+    n_sub_y: int
+    p: int
+    valid: "object"    # torch int32 [N] on the GPU, ascending
+    pupil: "object"    # torch uint8 [n_sub_y*p][n_sub_x*p] on the GPU
+
+    @classmethod
+    def from_numpy(cls, pupil: np.ndarray, p: int, valid: np.ndarray, device="cuda"):
+        torch = _torch()
+        H, W = pupil.shape
+        return cls(W // p, H // p, p,
+                   torch.from_numpy(np.ascontiguousarray(valid, dtype=np.int32)).to(device),
+                   torch.from_numpy(np.ascontiguousarray(pupil, dtype=np.uint8)).to(device))
+
+    @property
+    def n_valid(self) -> int:
+        return int(self.valid.numel())
+
+    @property
+    def shape(self) -> Tuple[int, int]:
+        return self.n_sub_y * self.p, self.n_sub_x * self.p
+
+    def struct(self) -> _abi.SynimWfs:
+        return _abi.SynimWfs(self.n_sub_x, self.n_sub_y, self.p, self.n_valid,
+                             self.valid.data_ptr(), self.pupil.data_ptr())
+
+
+# ---------------------------------------------------------- standalone steps
+def affine_warp(ifs, A, H_out: int, W_out: int, halo: int = 1, out=None, oob=None):
+    """Bilinear resampling of ifs [n][H_in][W_in] -> [n][H_out+2h][W_out+2h]."""
+    torch = _torch()
+    lib = load()
+    _dev_f32(ifs, "ifs")
+    n, H_in, W_in = ifs.shape
+    if out is None:
+        out = torch.empty((n, H_out + 2 * halo, W_out + 2 * halo), dtype=torch.float32,
+                          device=ifs.device)
+    a = _affine_struct(A)
+    _check(lib.synim_affine_warp(ifs.data_ptr(), n, H_in, W_in, C.byref(a), H_out, W_out, halo,
+                                 out.data_ptr(), oob.data_ptr() if oob is not None else None,
+                                 _stream_handle(ifs.device)), "affine_warp")
+    return out
+
+
+def sa_slopes(phase, wfs: Wfs, out=None):
+    """Slopes [n][2N] of haloed phase maps [n][H+2][W+2]."""
+    torch = _torch()
+    lib = load()
+    _dev_f32(phase, "phase")
+    n = phase.shape[0]
+    H, W = wfs.shape
+    if tuple(phase.shape[1:]) != (H + 2, W + 2):
+        raise ValueError("phase must be [n][H+2][W+2]")
+    if out is None:
+        out = torch.empty((n, 2 * wfs.n_valid), dtype=torch.float32, device=phase.device)
+    s = wfs.struct()
+    _check(lib.synim_sa_slopes(phase.data_ptr(), n, C.byref(s), out.data_ptr(),
+                               _stream_handle(phase.device)), "sa_slopes")
+    return out
+
+
+# ------------------------------------------------------------------ fused path
+def im_workspace_bytes(wfs: Wfs, A, planes: int = 1) -> int:
+    lib = load()
+    s = wfs.struct()
+    a = _affine_struct(A)
+    n = C.c_size_t(0)
+    _check(lib.synim_im_workspace(C.byref(s), C.byref(a), planes, C.byref(n)), "im_workspace")
+    return int(n.value)
+
+
+def _workspace(wfs, A, planes, ws, device):
+    torch = _torch()
+    need = im_workspace_bytes(wfs, A, planes)
+    if ws is None or ws.numel() < need:
+        ws = torch.empty(need, dtype=torch.uint8, device=device)
+    return ws
+
+
+def im_build(ifs, A, wfs: Wfs, out=None, ws=None):
+    """IM [n_act][2N] (actuator-major) of ifs [n_act][H_in][W_in]."""
+    torch = _torch()
+    lib = load()
+    _dev_f32(ifs, "ifs")
+    n, H_in, W_in = ifs.shape
+    if out is None:
+        out = torch.empty((n, 2 * wfs.n_valid), dtype=torch.float32, device=ifs.device)
+    ws = _workspace(wfs, A, 1, ws, ifs.device)
+    s = wfs.struct()
+    a = _affine_struct(A)
+    _check(lib.synim_im_build(ifs.data_ptr(), n, H_in, W_in, C.byref(a), C.byref(s),
+                              out.data_ptr(), ws.data_ptr(), ws.numel(),
+                              _stream_handle(ifs.device)), "im_build")
+    return out
+
+
+def _dA_structs(dA):
+    arr = (_abi.SynimAffine * 4)()
+    for j in range(4):
+        arr[j] = _affine_struct(dA[j])
+    return arr
+
+
+def im_jacobian(ifs, A, dA, wfs: Wfs, with_im: bool = True, ws=None):
+    """(IM or None, dIM [4][n_act][2N]) for the derivative maps dA [4x2x3]."""
+    torch = _torch()
+    lib = load()
+    _dev_f32(ifs, "ifs")
+    n, H_in, W_in = ifs.shape
+    nv2 = 2 * wfs.n_valid
+    im = torch.empty((n, nv2), dtype=torch.float32, device=ifs.device) if with_im else None
+    dim = torch.empty((4, n, nv2), dtype=torch.float32, device=ifs.device)
+    ws = _workspace(wfs, A, 5, ws, ifs.device)
+    s = wfs.struct()
+    a = _affine_struct(A)
+    _check(lib.synim_im_jacobian(ifs.data_ptr(), n, H_in, W_in, C.byref(a), _dA_structs(dA),
+                                 C.byref(s), im.data_ptr() if im is not None else None,
+                                 dim.data_ptr(), ws.data_ptr(), ws.numel(),
+                                 _stream_handle(ifs.device)), "im_jacobian")
+    return im, dim
+
+
+def im_vjp(ifs, A, dA, wfs: Wfs, grad_im, ws=None):
+    """grad_theta [4] (float64, device) = <grad_im, dIM/dtheta_j>."""
+    torch = _torch()
+    lib = load()
+    _dev_f32(ifs, "ifs")
+    _dev_f32(grad_im, "grad_im")
+    n, H_in, W_in = ifs.shape
+    out = torch.empty(4, dtype=torch.float64, device=ifs.device)
+    ws = _workspace(wfs, A, 5, ws, ifs.device)
+    s = wfs.struct()
+    a = _affine_struct(A)
+    _check(lib.synim_im_vjp(ifs.data_ptr(), n, H_in, W_in, C.byref(a), _dA_structs(dA),
+                            C.byref(s), grad_im.data_ptr(), out.data_ptr(), ws.data_ptr(),
+                            ws.numel(), _stream_handle(ifs.device)), "im_vjp")
+    return out
+
+
+def im_plan(wfs: Wfs, A, dA=None, planes: int = 1, ws=None, device="cuda"):
+    """Build the folded-geometry plan in a (new or given) workspace tensor."""
+    lib = load()
+    ws = _workspace(wfs, A, planes, ws, device)
+    s = wfs.struct()
+    a = _affine_struct(A)
+    d = _dA_structs(dA) if dA is not None else None
+    _check(lib.synim_im_plan(C.byref(s), C.byref(a), d, planes, ws.data_ptr(), ws.numel(),
+                             _stream_handle(ws.device)), "im_plan")
+    return ws
+
+
+def im_apply(ifs, A, wfs: Wfs, ws, planes: int = 1, plane: int = 0, out=None):
+    """Stream ifs through one plane of a plan built by :func:`im_plan`."""
+    torch = _torch()
+    lib = load()
+    _dev_f32(ifs, "ifs")
+    n, H_in, W_in = ifs.shape
+    if out is None:
+        out = torch.empty((n, 2 * wfs.n_valid), dtype=torch.float32, device=ifs.device)
+    s = wfs.struct()
+    a = _affine_struct(A)
+    _check(lib.synim_im_apply(ifs.data_ptr(), n, H_in, W_in, C.byref(a), C.byref(s), planes,
+                              plane, out.data_ptr(), ws.data_ptr(), ws.numel(),
+                              _stream_handle(ifs.device)), "im_apply")
+    return out
+
+
+def plan_status(ws) -> int:
+    """Device status word of the last plan built in ``ws`` (synchronises)."""
+    lib = load()
+    v = C.c_int(0)
+    _check(lib.synim_plan_status(ws.data_ptr(), C.byref(v), _stream_handle(ws.device)),
+           "plan_status")
+    return int(v.value)

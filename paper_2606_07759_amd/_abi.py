@@ -1,0 +1,68 @@
+"""ctypes declarations of the C ABI in ``include/synim.h`` (marshalling only)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsynim.so")
+
+
+class SynimAffine(C.Structure):
+    _fields_ = [("A", (C.c_double * 2) * 2), ("b", C.c_double * 2)]
+
+
+class SynimMisreg(C.Structure):
+    _fields_ = [("shift_x", C.c_double), ("shift_y", C.c_double), ("rot", C.c_double),
+                ("mag", C.c_double)]
+
+
+class SynimGeometry(C.Structure):
+    _fields_ = [(n, C.c_double) for n in (
+        "dm_shift_x", "dm_shift_y", "dm_rot", "dm_mag", "cone_scale", "footprint_x",
+        "footprint_y", "wfs_shift_x", "wfs_shift_y", "wfs_rot", "wfs_mag_x", "wfs_mag_y",
+        "kappa")]
+
+
+class SynimWfs(C.Structure):
+    _fields_ = [("n_sub_x", C.c_int32), ("n_sub_y", C.c_int32), ("p", C.c_int32),
+                ("n_valid", C.c_int32), ("valid_idx", C.c_void_p), ("pupil", C.c_void_p)]
+
+
+P = C.c_void_p
+I = C.c_int
+SZ = C.c_size_t
+
+# name -> (restype, argtypes); every function declared in include/synim.h
+SIGNATURES = {
+    "synim_status_str": (C.c_char_p, [I]),
+    "synim_version": (I, []),
+    "synim_affine_from_misreg": (I, [C.POINTER(SynimMisreg), I, I, I, I, C.c_double,
+                                     C.POINTER(SynimAffine), C.POINTER(SynimAffine)]),
+    "synim_affine_from_geometry": (I, [C.POINTER(SynimGeometry), I, I, I, I,
+                                       C.POINTER(SynimAffine)]),
+    "synim_affine_warp": (I, [P, I, I, I, C.POINTER(SynimAffine), I, I, I, P, P, P]),
+    "synim_sa_slopes": (I, [P, I, C.POINTER(SynimWfs), P, P]),
+    "synim_im_workspace": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), I, C.POINTER(SZ)]),
+    "synim_im_build": (I, [P, I, I, I, C.POINTER(SynimAffine), C.POINTER(SynimWfs), P, P, SZ, P]),
+    "synim_im_jacobian": (I, [P, I, I, I, C.POINTER(SynimAffine), C.POINTER(SynimAffine),
+                              C.POINTER(SynimWfs), P, P, P, SZ, P]),
+    "synim_im_vjp": (I, [P, I, I, I, C.POINTER(SynimAffine), C.POINTER(SynimAffine),
+                         C.POINTER(SynimWfs), P, P, P, SZ, P]),
+    "synim_im_plan": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(SynimAffine),
+                          I, P, SZ, P]),
+    "synim_im_apply": (I, [P, I, I, I, C.POINTER(SynimAffine), C.POINTER(SynimWfs), I, I, P, P,
+                           SZ, P]),
+    "synim_plan_status": (I, [P, C.POINTER(I), P]),
+}
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"HIP library not found at {path}; build it with `python -m paper_2606_07759_amd.build`")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib

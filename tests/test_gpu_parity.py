@@ -1,0 +1,198 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Tolerance (FP32 path vs FP64 oracle): max|dIM| <= 1e-5 * max|IM| for IMs and
+slopes; the standalone warp is held to 1e-6 of the IF maximum (a bilinear
+sample of FP32 data with FP32 weights); Jacobian planes to 1e-4 * max|J_j|.
+Sizes span several tiles, a ragged tail and non-multiple-of-4 IF rows; the
+ELT-scale workload is checked at full size on sampled actuator columns that the
+oracle computes one by one.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import workloads as wl
+from oracle import geometry as og, im as oim, slopes as osl, warp as owarp
+
+pytestmark = pytest.mark.gpu
+
+IM_TOL = 1e-5
+J_TOL = 1e-4
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def S(gpu_lib):
+    return gpu_lib
+
+
+def to_dev(x, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(x))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def rel_err(got, ref):
+    return float(np.max(np.abs(got - ref)) / np.max(np.abs(ref)))
+
+
+def small_cases():
+    """(name, pupil, p, valid, F, theta) covering tiles, ragged tails and OOB."""
+    out = []
+    cfg = wl.scao_small()
+    out.append(("scao_8x8", cfg.pupil, 10, cfg.valid, wl.if_stack(cfg.grid), cfg.theta))
+    rng = np.random.default_rng(11)
+    pup = wl.pupil_mask(65, 60.0, 0.3, (1.3, -0.7))
+    val = wl.valid_subapertures(pup, 5)
+    F = rng.standard_normal((7, 70, 71)).astype(np.float32)
+    out.append(("ragged_13x13_p5_w71", pup, 5, val, F, (0.37, -0.81, 0.12, 1.03)))
+    pup = wl.pupil_mask(48, 48.0, 0.2)
+    val = wl.valid_subapertures(pup, 4)
+    F = rng.standard_normal((3, 52, 52)).astype(np.float32)
+    out.append(("rot30_p4", pup, 4, val, F, (0.2, 0.1, math.radians(30.0), 1.1)))
+    # large shift: part of the window samples outside the IF grid (zero fill)
+    F = rng.standard_normal((2, 50, 50)).astype(np.float32)
+    out.append(("oob_shift_p4", pup, 4, val, F, (9.5, -7.25, math.radians(2.0), 0.95)))
+    out.append(("single_if_p10", cfg.pupil, 10, cfg.valid, wl.if_stack(cfg.grid)[40:41],
+                (0.0, 0.0, 0.0, 1.0)))
+    return out
+
+
+CASES = small_cases()
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_warp_parity(S, case):
+    import torch
+    name, pupil, p, valid, F, theta = case
+    say("warp", name)
+    H, W = pupil.shape
+    Hi, Wi = F.shape[1:]
+    A, _ = S.affine_from_misreg(theta, Hi, Wi, H, W)
+    oob = torch.zeros(1, dtype=torch.int32, device="cuda")
+    got = S.affine_warp(to_dev(F), A, H, W, halo=1, oob=oob).cpu().numpy()
+    ref, n_oob = owarp.warp(F, A[:, :2], A[:, 2], H, W, 1, count_oob=True)
+    assert np.max(np.abs(got - ref)) <= 1e-6 * np.abs(F).max()
+    assert int(oob.item()) == n_oob
+
+
+def test_warp_identity_and_quarter_turn_exact(S):
+    rng = np.random.default_rng(2)
+    F = rng.standard_normal((3, 96, 96)).astype(np.float32)
+    A, _ = S.affine_from_misreg((0, 0, 0, 1), 96, 96, 80, 80)
+    got = S.affine_warp(to_dev(F), A, 80, 80, halo=1).cpu().numpy()
+    assert np.array_equal(got, F[:, 7:89, 7:89])
+    F = rng.standard_normal((2, 40, 40)).astype(np.float32)
+    A, _ = S.affine_from_misreg((0, 0, math.pi / 2, 1), 40, 40, 40, 40)
+    got = S.affine_warp(to_dev(F), A, 40, 40, halo=0).cpu().numpy()
+    assert np.array_equal(got, np.rot90(F, -1, axes=(1, 2)))
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_slopes_parity(S, case):
+    name, pupil, p, valid, F, theta = case
+    say("slopes", name)
+    H, W = pupil.shape
+    rng = np.random.default_rng(5)
+    phase = rng.standard_normal((4, H + 2, W + 2)).astype(np.float32)
+    wfs = S.Wfs.from_numpy(pupil, p, valid)
+    got = S.sa_slopes(to_dev(phase), wfs).cpu().numpy()
+    ref = osl.slopes(phase, pupil, p, valid)
+    assert rel_err(got, ref) <= IM_TOL
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_im_build_parity(S, case):
+    name, pupil, p, valid, F, theta = case
+    say("im_build", name)
+    H, W = pupil.shape
+    Hi, Wi = F.shape[1:]
+    A, _ = S.affine_from_misreg(theta, Hi, Wi, H, W)
+    wfs = S.Wfs.from_numpy(pupil, p, valid)
+    ws = S.im_plan(wfs, A)
+    assert S.plan_status(ws) == 0
+    got = S.im_apply(to_dev(F), A, wfs, ws).cpu().numpy()
+    ref = oim.im_build(F, A[:, :2], A[:, 2], pupil, p, valid)
+    assert rel_err(got, ref) <= IM_TOL, rel_err(got, ref)
+    got2 = S.im_build(to_dev(F), A, wfs).cpu().numpy()
+    assert np.array_equal(got, got2)          # plan+apply == one-shot build, bitwise
+
+
+def test_fused_equals_warp_then_slopes(S):
+    cfg = wl.scao_small()
+    F = wl.if_stack(cfg.grid)
+    A, _ = S.affine_from_misreg(cfg.theta, 96, 96, 80, 80)
+    wfs = S.Wfs.from_numpy(cfg.pupil, 10, cfg.valid)
+    Fd = to_dev(F)
+    two = S.sa_slopes(S.affine_warp(Fd, A, 80, 80, 1), wfs).cpu().numpy()
+    one = S.im_build(Fd, A, wfs).cpu().numpy()
+    assert np.max(np.abs(two - one)) <= IM_TOL * np.abs(one).max()
+
+
+def test_im_build_deterministic(S):
+    cfg = wl.scao_small()
+    F = to_dev(wl.if_stack(cfg.grid))
+    A, _ = S.affine_from_misreg(cfg.theta, 96, 96, 80, 80)
+    wfs = S.Wfs.from_numpy(cfg.pupil, 10, cfg.valid)
+    a = S.im_build(F, A, wfs).cpu().numpy()
+    b = S.im_build(F, A, wfs).cpu().numpy()
+    assert np.array_equal(a, b)
+
+
+def test_jacobian_parity(S):
+    cfg = wl.scao_small()
+    F = wl.if_stack(cfg.grid)
+    A, dA = S.affine_from_misreg(cfg.theta, 96, 96, 80, 80)
+    wfs = S.Wfs.from_numpy(cfg.pupil, 10, cfg.valid)
+    im, dim = S.im_jacobian(to_dev(F), A, dA, wfs)
+    im = im.cpu().numpy()
+    dim = dim.cpu().numpy()
+    ref_J = oim.jacobian(F, cfg.theta, cfg.pupil, 10, cfg.valid)
+    ref_I = oim.im_build_misreg(F, cfg.theta, cfg.pupil, 10, cfg.valid)
+    assert rel_err(im, ref_I) <= IM_TOL
+    for j in range(4):
+        e = np.max(np.abs(dim[j] - ref_J[j])) / np.abs(ref_J[j]).max()
+        assert e <= J_TOL, (j, e)
+
+
+def test_vjp_parity(S):
+    cfg = wl.scao_small()
+    F = wl.if_stack(cfg.grid)
+    A, dA = S.affine_from_misreg(cfg.theta, 96, 96, 80, 80)
+    wfs = S.Wfs.from_numpy(cfg.pupil, 10, cfg.valid)
+    G = np.random.default_rng(4).standard_normal((81, 2 * cfg.n_valid)).astype(np.float32)
+    got = S.im_vjp(to_dev(F), A, dA, wfs, to_dev(G)).cpu().numpy()
+    ref = oim.vjp(G, oim.jacobian(F, cfg.theta, cfg.pupil, 10, cfg.valid))
+    # |<G, J_j>| can cancel; bound by the sum of |G||J_j| instead
+    Jr = oim.jacobian(F, cfg.theta, cfg.pupil, 10, cfg.valid)
+    for j in range(4):
+        scale = np.sum(np.abs(G) * np.abs(Jr[j]))
+        assert abs(got[j] - ref[j]) <= J_TOL * scale, (j, got[j], ref[j])
+
+
+def test_elt_full_size_sampled_columns(S):
+    import torch
+    cfg = wl.scao_elt(0)
+    say("elt: generating IF stack on device", cfg.grid.n_act)
+    Fd = wl.if_stack_torch(cfg.grid, "cuda")
+    A, _ = S.affine_from_misreg(cfg.theta, 512, 512, 480, 480)
+    wfs = S.Wfs.from_numpy(cfg.pupil, 6, cfg.valid)
+    ws = S.im_plan(wfs, A)
+    assert S.plan_status(ws) == 0
+    im = S.im_apply(Fd, A, wfs, ws)
+    torch.cuda.synchronize()
+    say("elt: built", tuple(im.shape))
+    rng = np.random.default_rng(7)
+    cols = sorted(set([0, cfg.grid.n_act - 1, 2628] + list(rng.choice(cfg.grid.n_act, 5, replace=False))))
+    got = im[cols].cpu().numpy()
+    Fs = np.stack([wl.if_single(cfg.grid, a) for a in cols])
+    ref = oim.im_build(Fs, A[:, :2], A[:, 2], cfg.pupil, 6, cfg.valid)
+    assert rel_err(got, ref) <= IM_TOL, rel_err(got, ref)
+    del Fd
