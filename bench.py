@@ -106,7 +106,7 @@ def cpu_baseline(seed: int, target_s: float):
     t1 = _oracle_chunk((seed, list(range(chunk))))
     per_col = t1 / chunk
     n_cols = int(max(workers * chunk, min(5257, target_s * workers / per_col)))
-    n_cols = (n_cols + chunk - 1) // chunk * chunk
+    n_cols = min(5256, (n_cols + chunk - 1) // chunk * chunk)
     cols = np.linspace(0, 5256, n_cols).astype(int).tolist()
     jobs = [(seed, cols[i:i + chunk]) for i in range(0, n_cols, chunk)]
     log(f"cpu baseline: {n_cols} columns on {workers} workers (~{per_col:.3f} s/column/core)")
@@ -143,7 +143,19 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": src.numel() * 4,
+                          "copy_probe_bytes_written": dst.numel() * 4}), flush=True)
+        return
     if args.gpus != 1:
         print("bench.py measures one GPU: the IM build shards by actuator columns with no "
               "exchange, so only --gpus 1 is run here", file=sys.stderr)

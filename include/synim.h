@@ -201,6 +201,33 @@ int synim_im_apply(const float* ifs, int n_act, int H_in, int W_in, const synim_
                    const synim_wfs* wfs, int planes, int plane, float* out, const void* ws,
                    size_t ws_bytes, void* stream);
 
+/* ------------------------------------------------------------- autotuner */
+
+/* Time up to max_candidates (variant x tile shape) configurations of the
+ * streaming kernel for this geometry on the caller's IF stack and record the
+ * fastest in a process-wide cache keyed by the WFS shape and the map's linear
+ * part; later plan/apply/build calls with that key use it.  im and ws are
+ * overwritten (ws sized by synim_im_workspace, which already covers every
+ * candidate).  times_ms (host, [max_candidates]) and n_tried (host) may be
+ * NULL.  Synchronises `stream`.  Errors: as synim_im_build. */
+int synim_im_autotune(const float* ifs, int n_act, int H_in, int W_in, const synim_affine* A,
+                      const synim_wfs* wfs, float* im, void* ws, size_t ws_bytes,
+                      int max_candidates, float* times_ms, int* n_tried, void* stream);
+
+/* The configuration plan/apply would use now: out7 (host) = block size,
+ * lanes per subaperture, patch rows, patch columns, tile width and height in
+ * subapertures, pipeline stages. */
+int synim_im_config(const synim_wfs* wfs, const synim_affine* A, int* out7);
+
+/* The candidate configurations synim_im_autotune tries, in its order (cost
+ * model first): out7 (host, [max_out][7]) as synim_im_config; *n_out (host)
+ * receives the count written. */
+int synim_im_candidates(const synim_wfs* wfs, const synim_affine* A, int* out7, int max_out,
+                        int* n_out);
+
+/* Forget every autotuned configuration. */
+void synim_autotune_clear(void);
+
 /* Device status word of the last plan built in `ws`: bit 0 a weight patch was
  * too small for the map, bit 1 a tile bounding box overflowed (that tile's
  * slopes are not written), bit 2 a valid subaperture has no pupil pixel (its

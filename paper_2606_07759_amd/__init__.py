@@ -270,6 +270,55 @@ def im_apply(ifs, A, wfs: Wfs, ws, planes: int = 1, plane: int = 0, out=None):
     return out
 
 
+def im_autotune(ifs, A, wfs: Wfs, max_candidates: int = 8, ws=None):
+    """Time candidate kernel configurations on ``ifs`` and cache the fastest.
+
+    Returns the list of per-candidate times (ms) in the order tried."""
+    torch = _torch()
+    lib = load()
+    _dev_f32(ifs, "ifs")
+    n, H_in, W_in = ifs.shape
+    out = torch.empty((n, 2 * wfs.n_valid), dtype=torch.float32, device=ifs.device)
+    ws = _workspace(wfs, A, 1, ws, ifs.device)
+    times = (C.c_float * max_candidates)()
+    tried = C.c_int(0)
+    s = wfs.struct()
+    a = _affine_struct(A)
+    _check(lib.synim_im_autotune(ifs.data_ptr(), n, H_in, W_in, C.byref(a), C.byref(s),
+                                 out.data_ptr(), ws.data_ptr(), ws.numel(), max_candidates, times,
+                                 C.byref(tried), _stream_handle(ifs.device)), "im_autotune")
+    return [float(times[i]) for i in range(tried.value)]
+
+
+_CFG_KEYS = ("block", "lanes_per_subap", "patch_rows", "patch_cols", "tile_x", "tile_y", "stages")
+
+
+def im_config(wfs: Wfs, A) -> dict:
+    """Kernel configuration plan/apply would use for this geometry now."""
+    lib = load()
+    o = (C.c_int * 7)()
+    s = wfs.struct()
+    a = _affine_struct(A)
+    _check(lib.synim_im_config(C.byref(s), C.byref(a), o), "im_config")
+    return dict(zip(_CFG_KEYS, o[:7]))
+
+
+def im_candidates(wfs: Wfs, A, max_out: int = 48) -> list:
+    """Candidate kernel configurations in the autotuner's order."""
+    lib = load()
+    o = (C.c_int * (7 * max_out))()
+    n = C.c_int(0)
+    s = wfs.struct()
+    a = _affine_struct(A)
+    _check(lib.synim_im_candidates(C.byref(s), C.byref(a), o, max_out, C.byref(n)),
+           "im_candidates")
+    return [dict(zip(_CFG_KEYS, o[7 * i:7 * i + 7])) for i in range(n.value)]
+
+
+def autotune_clear():
+    load().synim_autotune_clear()
+
+
 def plan_status(ws) -> int:
     """Device status word of the last plan built in ``ws`` (synchronises)."""
     lib = load()

@@ -53,6 +53,12 @@ SIGNATURES = {
     "synim_im_apply": (I, [P, I, I, I, C.POINTER(SynimAffine), C.POINTER(SynimWfs), I, I, P, P,
                            SZ, P]),
     "synim_plan_status": (I, [P, C.POINTER(I), P]),
+    "synim_im_autotune": (I, [P, I, I, I, C.POINTER(SynimAffine), C.POINTER(SynimWfs), P, P, SZ,
+                              I, C.POINTER(C.c_float), C.POINTER(I), P]),
+    "synim_im_config": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(I)]),
+    "synim_autotune_clear": (None, []),
+    "synim_im_candidates": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(I), I,
+                                C.POINTER(I)]),
 }
 
 

@@ -17,23 +17,26 @@
 //   plan_weights  one thread per patch entry gathers every (q, tap) that lands
 //                 on it; the Jacobian planes use d w_tap / d theta_j from the
 //                 floor-cell bilinear gradient and the derivative maps;
-//   plan_tiles    groups subapertures into tiles and computes each tile's IF
-//                 bounding box.
-// Stream (FP32, the hot loop): each workgroup owns one tile and a chunk of
-// actuators; its weights sit in registers, and every actuator's bounding box
-// is read from HBM once (coalesced float4 rows, double-buffered through LDS)
-// and contracted against the patches; partial sums of the LPS lanes that share
-// a subaperture are combined with DPP.
+//   plan_slots    groups subapertures into tiles;
+//   plan_rows     lists, for every tile, the IF rows its patches touch, each
+//                 trimmed to the columns they cover, packed for staging.
+// Stream (FP32, the hot loop): a persistent kernel hands out (actuator chunk,
+// tile) items from per-XCD queues.  For an item the workgroup loads the tile's
+// weights into registers, then streams every actuator's packed tile rows from
+// HBM into LDS with buffer->LDS DMA (three stages, two actuators in flight)
+// and contracts them against the patches; the LPS lanes that share a
+// subaperture combine their partial sums with DPP.
 #include <algorithm>
 #include <climits>
 #include <cmath>
+#include <mutex>
+#include <utility>
 
 #include "common.hpp"
 
 namespace synim {
 namespace {
 
-constexpr int BLOCK = 256;
 constexpr int GMAX_VJP = 16384;   // max workgroups of a VJP launch (partials buffer)
 
 struct Map4 {
@@ -165,41 +168,114 @@ __device__ int find_valid(const int32_t* __restrict__ valid, int nv, int k) {
   return -1;
 }
 
-__global__ void plan_tiles_kernel(const int32_t* __restrict__ valid, int nv, int n_sub_x,
+// One thread per (tile, slot): which valid subaperture (if any) the slot holds.
+__global__ void plan_slots_kernel(const int32_t* __restrict__ valid, int nv, int n_sub_x,
                                   int n_sub_y, int TX, int TY, int n_tiles_x, int n_tiles,
-                                  const int2* __restrict__ origin, int PH, int PW, int BWmax,
-                                  int BHmax, int* __restrict__ slot_kk, int4* __restrict__ bbox,
-                                  int* __restrict__ status) {
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  const int tu = t % n_tiles_x, tv = t / n_tiles_x;
+                                  int* __restrict__ slot_kk) {
   const int NS = TX * TY;
-  int xmin = INT_MAX, ymin = INT_MAX, xmax = INT_MIN, ymax = INT_MIN;
-  for (int s = 0; s < NS; ++s) {
-    const int u = tu * TX + s % TX, v = tv * TY + s / TX;
-    int kk = -1;
-    if (u < n_sub_x && v < n_sub_y) kk = find_valid(valid, nv, v * n_sub_x + u);
-    slot_kk[(size_t)t * NS + s] = kk;
+  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (gid >= (long)n_tiles * NS) return;
+  const int t = (int)(gid / NS), s = (int)(gid - (long)t * NS);
+  const int tu = t % n_tiles_x, tv = t / n_tiles_x;
+  const int u = tu * TX + s % TX, v = tv * TY + s / TX;
+  int kk = -1;
+  if (u < n_sub_x && v < n_sub_y) kk = find_valid(valid, nv, v * n_sub_x + u);
+  slot_kk[gid] = kk;
+}
+
+__device__ __forceinline__ int wave_min(int v) {
+  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_max(int v) {
+  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+constexpr int MAX_TILE_ROWS = 512;
+
+// One workgroup per tile: the IF rows its patches touch, each trimmed to the
+// column interval those patches cover (aligned to 4 floats), packed one after
+// the other.  tile_info[t] = (y0, rows, packed floats, 0), rows = 0 for an empty
+// tile; rows[t*BHmax + r] = (first column of row r, packed offset of row r).
+__global__ __launch_bounds__(256) void plan_rows_kernel(int NS, const int* __restrict__ slot_kk,
+                                                        const int2* __restrict__ origin, int PH,
+                                                        int PW, int BHmax, int cap_floats,
+                                                        int4* __restrict__ tile_info,
+                                                        int2* __restrict__ rows,
+                                                        int* __restrict__ status) {
+  __shared__ int s_ox[1024], s_oy[1024];
+  __shared__ int s_x0[MAX_TILE_ROWS], s_w[MAX_TILE_ROWS];
+  __shared__ int s_ymin, s_ymax;
+  const int t = blockIdx.x, tid = threadIdx.x;
+  if (tid == 0) {
+    s_ymin = INT_MAX;
+    s_ymax = INT_MIN;
+  }
+  __syncthreads();
+  for (int s = tid; s < NS; s += blockDim.x) {
+    const int kk = slot_kk[(size_t)t * NS + s];
+    int2 o = make_int2(INT_MIN, INT_MIN);
     if (kk >= 0) {
-      const int2 o = origin[kk];
-      xmin = min(xmin, o.x);
-      ymin = min(ymin, o.y);
-      xmax = max(xmax, o.x);
-      ymax = max(ymax, o.y);
+      o = origin[kk];
+      atomicMin(&s_ymin, o.y);
+      atomicMax(&s_ymax, o.y);
     }
+    s_ox[s] = o.x;
+    s_oy[s] = o.y;
   }
-  int4 bb = make_int4(0, 0, 0, 0);
-  if (xmin != INT_MAX) {
-    const int x0 = floor_div(xmin, 4) * 4;
-    const int bw = ((xmax + PW - x0) + 3) / 4 * 4;
-    const int bh = ymax + PH - ymin;
-    if (bw > BWmax || bh > BHmax) {
-      atomicOr(status, 2);   // tile skipped: its slopes stay unwritten
+  __syncthreads();
+  const int y0 = s_ymin;
+  if (y0 == INT_MAX) {
+    if (tid == 0) tile_info[t] = make_int4(0, 0, 0, 0);
+    return;
+  }
+  const int bh = s_ymax + PH - y0;
+  if (bh > BHmax || bh > MAX_TILE_ROWS) {
+    if (tid == 0) {
+      atomicOr(status, 2);
+      tile_info[t] = make_int4(0, 0, 0, 0);
+    }
+    return;
+  }
+  for (int r = tid; r < bh; r += blockDim.x) {
+    const int y = y0 + r;
+    int lo = INT_MAX, hi = INT_MIN;
+    for (int s = 0; s < NS; ++s) {
+      const int oy = s_oy[s];
+      if (oy != INT_MIN && oy <= y && y < oy + PH) {
+        lo = min(lo, s_ox[s]);
+        hi = max(hi, s_ox[s] + PW);
+      }
+    }
+    if (lo == INT_MAX) {
+      s_x0[r] = 0;
+      s_w[r] = 0;
     } else {
-      bb = make_int4(x0, ymin, bw, bh);
+      const int x0 = floor_div(lo, 4) * 4;
+      s_x0[r] = x0;
+      s_w[r] = (hi - x0 + 3) / 4 * 4;
     }
   }
-  bbox[t] = bb;
+  __syncthreads();
+  if (tid == 0) {
+    int off = 0;
+    for (int r = 0; r < bh; ++r) {
+      rows[(size_t)t * BHmax + r] = make_int2(s_x0[r], off);
+      off += s_w[r];
+    }
+    if (off > cap_floats) {
+      atomicOr(status, 2);   // tile skipped: its slopes stay unwritten
+      tile_info[t] = make_int4(0, 0, 0, 0);
+    } else {
+      tile_info[t] = make_int4(y0, bh, off, 0);
+    }
+  }
+}
+
+__global__ void zero_ints_kernel(int* __restrict__ p, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
 }
 
 // ------------------------------------------------------------------ streaming
@@ -219,12 +295,12 @@ struct StreamArgs {
   const int2* origin;
   const float* weights;      // plane 0 base
   const int* slot_kk;
-  const int4* bbox;
-  int nv, n_tiles, chunk, n_chunks;
-  int ns;                    // subapertures per tile (TX*TY <= BLOCK/LPS)
-  int S;                     // LDS row stride (floats, multiple of 4)
+  const int4* tile_info;
+  const int2* rows;
   int BHmax;
-  int vec_ok;                // IF rows are 16-byte aligned float4 rows
+  int nv, n_tiles, ns, chunk, n_chunks;
+  int* counters;             // [gridDim.z][8] work counters, zeroed before the launch
+  float* scratch;            // 64 floats that absorb the stores of idle lanes
   int plane0;                // first weight plane handled (blockIdx.z adds to it)
   int out_plane0;            // weight plane that lands in out[0]
   float* out;                // [plane - out_plane0][n_act][2nv]
@@ -232,154 +308,216 @@ struct StreamArgs {
   double* partials;          // VJP: [4][gridDim.x]
 };
 
-template <int LPS, int RPL, int PW, int NPF, bool VJP>
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// s_waitcnt immediates (gfx9 encoding) that wait on vmcnt only.
+constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14); }
+
+// Streams one actuator's packed tile rows into an LDS stage buffer with
+// buffer->LDS DMA.  Each wave issues exactly NJ instructions per stage, so the
+// number of vector-memory operations in flight is known at compile time.  The
+// buffer resource covers the actuator's IF plane only: rows above/below the
+// grid fall outside its range and read as zero; columns outside the grid are
+// sent out of range explicitly.
+template <int BLOCK, int NJ, int VW>
+__device__ __forceinline__ void stage_issue(const float* plane_ptr, int plane_bytes,
+                                            const unsigned* voff, float4* buf, int wave) {
+  __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(plane_ptr), (short)0, plane_bytes,
+                                        0x00020000);
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    float* dst = reinterpret_cast<float*>(buf) + (size_t)(BLOCK * j + 64 * wave) * VW;
+    if constexpr (VW == 4)
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)dst, 16, voff[j], 0, 0, 0);
+    else
+      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)dst, 4, voff[j], 0, 0, 0);
+  }
+}
+
+// Stage buffer K of a pipeline: one distinct __shared__ object per K, so the
+// compiler can tell that reading one stage never aliases the DMA in flight
+// into another (with one shared array it would drain every DMA before each
+// LDS read).
+template <int K, int F4>
+__device__ __forceinline__ float4* stage_buf() {
+  __shared__ float4 b[F4];
+  return b;
+}
+
+// s_waitcnt vmcnt(n) for a uniform runtime n in [0, 63] (the immediate must be
+// a constant: a jump table over every value).
+__device__ __forceinline__ void wait_vm(int n) {
+  switch (n) {
+#define SYNIM_W(k) case k: __builtin_amdgcn_s_waitcnt(waitcnt_vm(k)); break;
+#define SYNIM_W8(k) SYNIM_W(k) SYNIM_W(k + 1) SYNIM_W(k + 2) SYNIM_W(k + 3) SYNIM_W(k + 4) \
+    SYNIM_W(k + 5) SYNIM_W(k + 6) SYNIM_W(k + 7)
+    SYNIM_W8(0) SYNIM_W8(8) SYNIM_W8(16) SYNIM_W8(24) SYNIM_W8(32) SYNIM_W8(40) SYNIM_W8(48)
+    SYNIM_W8(56)
+#undef SYNIM_W8
+#undef SYNIM_W
+    default: __builtin_amdgcn_s_waitcnt(waitcnt_vm(0)); break;
+  }
+}
+
+// Persistent streaming kernel.  Work items are (actuator chunk, tile) pairs;
+// workgroup b serves the queue of its XCD (b mod 8 - consecutive workgroups are
+// dispatched round-robin over the 8 XCDs), and each queue walks its chunks in
+// order, tiles fastest, so the tiles of one chunk run side by side on one XCD
+// and share the IF rows of their halos in that XCD's L2.  Within an item the
+// actuators stream through NST LDS stages with NST-1 actuators in flight.
+template <int BLOCK, int LPS, int RPL, int PW, int NJ, int VW, int NST, bool VJP>
 __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
   constexpr int PH = LPS * RPL;
   constexpr int E = PH * PW;
-  extern __shared__ float4 lds4[];
-  float* lds = reinterpret_cast<float*>(lds4);
-
-  // XCD-aware mapping: consecutive workgroups go round-robin over the 8 XCDs,
-  // so give each XCD a contiguous range of (chunk, tile) work; the tiles of one
-  // actuator chunk then run side by side and share their halo rows in L2.
-  const int G = gridDim.x;
-  const int per = G / 8;
-  const int logical = (blockIdx.x % 8) * per + blockIdx.x / 8;
-  const int total = g.n_tiles * g.n_chunks;
-  if (logical >= total) {
-    if (VJP && threadIdx.x == 0)
-      g.partials[(size_t)(g.plane0 + blockIdx.z - 1) * G + blockIdx.x] = 0.0;
-    return;
-  }
-  const int chunk_id = logical / g.n_tiles;
-  const int tile = logical - chunk_id * g.n_tiles;
-  const int plane = g.plane0 + blockIdx.z;
-  const int4 bb = g.bbox[tile];
+  constexpr int STAGE_F4 = NJ * BLOCK * VW / 4;   // float4 per stage buffer
+  static_assert(NST >= 2 && NST <= 8, "2..8 stages");
+  static_assert(NJ * (NST - 2) <= 63, "vmcnt range");
+  __shared__ int s_item;
+  __shared__ double s_red[BLOCK / 64];
 
   const int tid = threadIdx.x;
+  const int wave = tid >> 6;
   const int slot = tid / LPS, q = tid % LPS;
-  const int kk = (bb.z > 0 && slot < g.ns) ? g.slot_kk[(size_t)tile * g.ns + slot] : -1;
-
+  const int xcd = blockIdx.x & 7;
+  const int plane = g.plane0 + blockIdx.z;
+  const int nc_x = g.n_chunks > xcd ? (g.n_chunks - xcd + 7) / 8 : 0;
+  const int n_items = nc_x * g.n_tiles;
+  int* ctr = g.counters + 8 * blockIdx.z + xcd;
+  const int plane_bytes = g.H_in * g.W_in * 4;
+  const size_t plane_in = (size_t)g.H_in * g.W_in;
   double vacc = 0.0;
-  if (bb.z > 0) {
-    const int x0 = bb.x, y0 = bb.y, bw = bb.z, bh = bb.w;
-    const int S = g.S;
-    const int buf_stride = g.BHmax * S;
+
+  for (;;) {
+    __syncthreads();   // the previous item's stage buffers are free again
+    if (tid == 0) s_item = atomicAdd(ctr, 1);
+    __syncthreads();
+    const int item = s_item;
+    if (item >= n_items) break;
+    const int m = item / g.n_tiles;
+    const int tile = item - m * g.n_tiles;
+    const int chunk_id = xcd + 8 * m;
+    const int4 ti = g.tile_info[tile];
+    if (ti.y == 0) continue;   // empty tile
+    const int y0 = ti.x, nfl = ti.z;
+    const int kk = slot < g.ns ? g.slot_kk[(size_t)tile * g.ns + slot] : -1;
+    const int2* rows = g.rows + (size_t)tile * g.BHmax;
 
     float wx[RPL][PW], wy[RPL][PW];
-    int lbase = 0;
+    int base[RPL];
     if (kk >= 0) {
       const int2 o = g.origin[kk];
-      lbase = (o.y - y0 + q) * S + (o.x - x0);
       const float* W = g.weights + ((size_t)plane * g.nv + kk) * 2 * E;
 #pragma unroll
-      for (int i = 0; i < RPL; ++i)
+      for (int i = 0; i < RPL; ++i) {
+        const int2 rw = rows[o.y - y0 + q + LPS * i];
+        base[i] = rw.y + (o.x - rw.x);
 #pragma unroll
         for (int c = 0; c < PW; ++c) {
           wx[i][c] = W[(q + LPS * i) * PW + c];
           wy[i][c] = W[E + (q + LPS * i) * PW + c];
         }
+      }
     } else {
 #pragma unroll
-      for (int i = 0; i < RPL; ++i)
+      for (int i = 0; i < RPL; ++i) {
+        base[i] = 0;
 #pragma unroll
         for (int c = 0; c < PW; ++c) wx[i][c] = wy[i][c] = 0.f;
-    }
-
-    // this thread's share of the bounding box: vectors tid + BLOCK*j
-    const int vpr = bw >> 2;   // float4 per bbox row
-    const int nvec = bh * vpr;
-    int goff[NPF], loff[NPF], kind[NPF];
-#pragma unroll
-    for (int j = 0; j < NPF; ++j) {
-      const int vi = tid + BLOCK * j;
-      const int r = vi / vpr, cv = vi - (vi / vpr) * vpr;
-      const int gy = y0 + r, gx = x0 + 4 * cv;
-      loff[j] = r * S + 4 * cv;
-      goff[j] = 0;
-      if (vi >= nvec) {
-        kind[j] = 0;
-      } else if (g.vec_ok && gy >= 0 && gy < g.H_in && gx >= 0 && gx + 3 < g.W_in) {
-        kind[j] = 1;
-        goff[j] = gy * g.W_in + gx;
-      } else {
-        kind[j] = 2;   // partly or fully outside the IF grid, or unaligned rows
-        goff[j] = gy * g.W_in + gx;
       }
     }
-    const size_t plane_in = (size_t)g.H_in * g.W_in;
+
+    // byte offsets (within one actuator plane) of this lane's DMA vectors;
+    // out-of-range offsets make the buffer unit return zeros
+    unsigned voff[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int fo = (BLOCK * j + tid) * VW;   // packed float offset of the vector
+      unsigned v = 0x80000000u;
+      if (fo < nfl) {
+        int lo = 0, hi = ti.y - 1;             // last row whose offset is <= fo
+        while (lo < hi) {
+          const int mid = (lo + hi + 1) >> 1;
+          if (rows[mid].y <= fo) lo = mid; else hi = mid - 1;
+        }
+        const int2 rw = rows[lo];
+        const int gx = rw.x + (fo - rw.y), gy = y0 + lo;
+        if (gx >= 0 && gx + VW <= g.W_in) v = (unsigned)(gy * g.W_in + gx) * 4u;
+      }
+      voff[j] = v;
+    }
     const int a0 = chunk_id * g.chunk;
     const int a1 = min(g.n_act, a0 + g.chunk);
 
-    float4 pf[NPF];
-    auto fetch = [&](int a) {
-      const float* F = g.ifs + (size_t)a * plane_in;
-#pragma unroll
-      for (int j = 0; j < NPF; ++j) {
-        if (kind[j] == 1) {
-          pf[j] = *reinterpret_cast<const float4*>(F + goff[j]);
-        } else if (kind[j] == 2) {
-          const int vi = tid + BLOCK * j;
-          const int r = vi / vpr, cv = vi - (vi / vpr) * vpr;
-          const int gy = y0 + r, gx = x0 + 4 * cv;
-          float t[4];
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int xx = gx + e;
-            t[e] = (gy >= 0 && gy < g.H_in && xx >= 0 && xx < g.W_in)
-                       ? F[(size_t)gy * g.W_in + xx]
-                       : 0.f;
-          }
-          pf[j] = make_float4(t[0], t[1], t[2], t[3]);
-        }
-      }
-    };
-
-    if (a0 < a1) fetch(a0);
-    for (int a = a0; a < a1; ++a) {
-      float* buf = lds + ((a - a0) & 1) * buf_stride;
-#pragma unroll
-      for (int j = 0; j < NPF; ++j)
-        if (kind[j]) *reinterpret_cast<float4*>(buf + loff[j]) = pf[j];
-      __syncthreads();
-      if (a + 1 < a1) fetch(a + 1);
-
+    auto consume = [&](const float4* buf, int a) {
+      const float* fb = reinterpret_cast<const float*>(buf);
       float sx = 0.f, sy = 0.f;
-      const float* rowp = buf + lbase;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
 #pragma unroll
         for (int c = 0; c < PW; ++c) {
-          const float f = rowp[i * LPS * S + c];
+          const float f = fb[base[i] + c];
           sx = __fmaf_rn(wx[i][c], f, sx);
           sy = __fmaf_rn(wy[i][c], f, sy);
         }
       }
       sx = dpp_sum(sx, LPS);
       sy = dpp_sum(sy, LPS);
-      if (kk >= 0) {
-        const size_t row = (size_t)a * 2 * g.nv;
-        if (VJP) {
-          if (q == 0) vacc += (double)g.grad[row + kk] * sx + (double)g.grad[row + g.nv + kk] * sy;
-        } else {
-          float* o = g.out + (size_t)(plane - g.out_plane0) * g.n_act * 2 * g.nv + row;
-          if (q == 0) o[kk] = sx;
-          if (q == 1) o[g.nv + kk] = sy;
-        }
+      const size_t row = (size_t)a * 2 * g.nv;
+      if (VJP) {
+        if (kk >= 0 && q == 0)
+          vacc += (double)g.grad[row + kk] * sx + (double)g.grad[row + g.nv + kk] * sy;
+      } else {
+        // exactly one store instruction per wave and actuator, whatever the
+        // lanes hold: lanes with nothing to write target a scratch slot.  The
+        // pipeline's wait counts rely on this number.
+        float* o = g.out + (size_t)(plane - g.out_plane0) * g.n_act * 2 * g.nv + row;
+        const bool real = kk >= 0 && q < 2;
+        float* dst = real ? (q == 0 ? o + kk : o + g.nv + kk) : g.scratch + (tid & 63);
+        __builtin_nontemporal_store(q == 0 ? sx : sy, dst);
       }
+    };
+    auto issue = [&](float4* buf, int a) {
+      stage_issue<BLOCK, NJ, VW>(g.ifs + (size_t)a * plane_in, plane_bytes, voff, buf, wave);
+    };
+    // one pipeline step for actuator a held in stage K: wait for it (the later
+    // stages already issued may stay in flight), make it visible to every
+    // wave, refill the stage freed by the previous step with actuator
+    // a+NST-1, then consume.  Vector-memory operations complete in issue
+    // order, so "at most n in flight", n = the operations issued after this
+    // stage's DMA, means this stage has landed.
+    // The wait counts every vector-memory operation issued after this stage's
+    // DMA: the later stages' DMA (NJ each) and, in the IM kernel, the one store
+    // of each step since then.
+    auto step = [&](auto kc, int a) {
+      constexpr int K = decltype(kc)::value;
+      const int later = min(NST - 2, a1 - 1 - a);
+      const int stores = VJP ? 0 : min(a - a0, NST - 1);
+      wait_vm(later * NJ + stores);
+      __builtin_amdgcn_s_barrier();
+      if (a + NST - 1 < a1) issue(stage_buf<(K + NST - 1) % NST, STAGE_F4>(), a + NST - 1);
+      consume(stage_buf<K, STAGE_F4>(), a);
+    };
+    [&]<int... K>(std::integer_sequence<int, K...>) {
+      ((a0 + K < a1 && K < NST - 1 ? issue(stage_buf<K, STAGE_F4>(), a0 + K) : void()), ...);
+    }(std::make_integer_sequence<int, NST>{});
+    for (int a = a0; a < a1; a += NST) {
+      [&]<int... K>(std::integer_sequence<int, K...>) {
+        ((a + K < a1 ? step(std::integral_constant<int, K>{}, a + K) : void()), ...);
+      }(std::make_integer_sequence<int, NST>{});
     }
   }
   if (VJP) {
-    // fixed-order block reduction of the per-lane accumulators
-    __shared__ double red[BLOCK];
+    // fixed-order reduction: butterfly within each wave, then over the waves
+    double v = vacc;
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((tid & 63) == 0) s_red[wave] = v;
     __syncthreads();
-    red[tid] = vacc;
-    __syncthreads();
-    for (int s = BLOCK / 2; s > 0; s >>= 1) {
-      if (tid < s) red[tid] += red[tid + s];
-      __syncthreads();
+    if (tid == 0) {
+      double s = 0.0;
+      for (int w = 0; w < BLOCK / 64; ++w) s += s_red[w];
+      g.partials[(size_t)(plane - 1) * gridDim.x + blockIdx.x] = s;
     }
-    if (tid == 0) g.partials[(size_t)(plane - 1) * G + blockIdx.x] = red[0];
   }
 }
 
@@ -403,18 +541,38 @@ __global__ void vjp_finalize_kernel(const double* __restrict__ partials, int G,
 using StreamFn = void (*)(StreamArgs);
 
 struct Variant {
-  int LPS, RPL, PW, NPF;
-  StreamFn im, vjp;
+  int BLOCK, LPS, RPL, PW, NJ4, NST;   // NJ4: 16-byte DMA instructions per wave per stage
+  StreamFn im4, vjp4;                  // 16-byte DMA: rows a multiple of 4 floats, aligned stack
+  StreamFn im1, vjp1;                  // 4-byte DMA: any row length / alignment
+  int PH() const { return LPS * RPL; }
+  int cap_floats() const { return NJ4 * BLOCK * 4; }
 };
 
-#define SYNIM_VARIANT(L, R, W, N) \
-  {L, R, W, N, im_stream_kernel<L, R, W, N, false>, im_stream_kernel<L, R, W, N, true>}
+// 4-byte DMA issues 4x the instructions per stage: cap its depth to what the
+// vmcnt counter can express
+constexpr int nst_vw1(int n, int s) { return s < 2 + 63 / (4 * n) ? s : 2 + 63 / (4 * n); }
 
-// ordered by cost: the first variant whose patch fits is used
+#define SYNIM_VARIANT(B, L, R, W, N, S)                                                \
+  {B, L, R, W, N, S, im_stream_kernel<B, L, R, W, N, 4, S, false>,                     \
+   im_stream_kernel<B, L, R, W, N, 4, S, true>,                                        \
+   im_stream_kernel<B, L, R, W, 4 * N, 1, nst_vw1(N, S), false>,                       \
+   im_stream_kernel<B, L, R, W, 4 * N, 1, nst_vw1(N, S), true>}
+
+// (block, lanes/subaperture, rows/lane, patch columns, DMA per wave per stage,
+// stages).  Three stages of small tiles let several workgroups share a CU;
+// deeper pipelines of one workgroup per CU keep more bytes in flight.
 const Variant kVariants[] = {
-    SYNIM_VARIANT(4, 2, 8, 4),  SYNIM_VARIANT(4, 3, 10, 4), SYNIM_VARIANT(4, 3, 12, 4),
-    SYNIM_VARIANT(8, 2, 12, 6), SYNIM_VARIANT(8, 2, 14, 6), SYNIM_VARIANT(8, 2, 16, 6),
-    SYNIM_VARIANT(8, 3, 20, 8), SYNIM_VARIANT(8, 3, 24, 8),
+    SYNIM_VARIANT(1024, 4, 2, 8, 3, 3),  SYNIM_VARIANT(512, 4, 2, 8, 3, 6),
+    SYNIM_VARIANT(256, 4, 2, 8, 4, 3),   SYNIM_VARIANT(256, 4, 2, 8, 4, 8),
+    SYNIM_VARIANT(1024, 4, 3, 10, 3, 3), SYNIM_VARIANT(512, 4, 3, 10, 3, 6),
+    SYNIM_VARIANT(512, 4, 3, 10, 2, 8),  SYNIM_VARIANT(256, 4, 3, 10, 4, 3),
+    SYNIM_VARIANT(256, 4, 3, 10, 4, 8),
+    SYNIM_VARIANT(1024, 4, 3, 12, 3, 3), SYNIM_VARIANT(512, 4, 3, 12, 3, 6),
+    SYNIM_VARIANT(256, 4, 3, 12, 4, 3),
+    SYNIM_VARIANT(512, 8, 2, 12, 3, 6),  SYNIM_VARIANT(256, 8, 2, 12, 6, 3),
+    SYNIM_VARIANT(512, 8, 2, 14, 3, 6),  SYNIM_VARIANT(256, 8, 2, 14, 6, 3),
+    SYNIM_VARIANT(512, 8, 2, 16, 3, 6),  SYNIM_VARIANT(256, 8, 2, 16, 6, 3),
+    SYNIM_VARIANT(256, 8, 3, 20, 6, 3),  SYNIM_VARIANT(256, 8, 3, 24, 6, 3),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -422,65 +580,123 @@ struct Dims {
   const Variant* var;
   int PH, PW;
   int TX, TY, NSLOT, n_tiles_x, n_tiles;
-  int BWmax, BHmax, S;
+  int BWmax, BHmax;
 };
 
 struct WsLayout {
-  size_t status, origin, inv2nk, weights, slot_kk, bbox, partials, total;
+  size_t status, counters, scratch, origin, inv2nk, weights, slot_kk, tile_info, rows, partials,
+      total;
 };
 
-int choose_dims(const synim_wfs& w, const synim_affine& A, Dims* d) {
+constexpr int MAX_PLANES = 5;
+
+// Every (variant, tile shape) that can run this geometry, cheapest first by the
+// cost model: the smallest weight patch that fits, then staged IF floats per
+// subaperture (a partial 128-byte line counted at each row end), for tiles
+// whose packed rows provably fit the stage buffers.
+int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double* cost_out,
+                   int max_out) {
   const double ax = std::fabs(A.A[0][0]) + std::fabs(A.A[0][1]);
   const double ay = std::fabs(A.A[1][0]) + std::fabs(A.A[1][1]);
   const int p = w.p;
   const int pw_need = (int)std::floor(ax * (p + 1) + 1e-7) + 3;
   const int ph_need = (int)std::floor(ay * (p + 1) + 1e-7) + 3;
-  const Variant* var = nullptr;
+  int best_area = INT_MAX;
   for (int i = 0; i < kNumVariants; ++i)
-    if (kVariants[i].PW >= pw_need && kVariants[i].LPS * kVariants[i].RPL >= ph_need) {
-      var = &kVariants[i];
-      break;
-    }
-  if (!var) return SYNIM_E_UNSUPPORTED;
-  const int nslot_max = BLOCK / var->LPS;
-  const int PH = var->LPS * var->RPL, PW = var->PW;
-  // tile shape: the TX x TY factorisation with the least staged IF area per
-  // covered subaperture whose bounding box fits the prefetch registers; full
-  // tiles (every lane busy) first, then half and quarter tiles for strongly
-  // rotated or magnified maps
-  int bt = -1, bns = 0, bBW = 0, bBH = 0;
-  for (int ns = nslot_max; ns >= nslot_max / 4 && bt < 0; ns /= 2) {
-    double best = 1e300;
-    for (int tx = 1; tx <= ns; tx *= 2) {
-      const int ty = ns / tx;
-      const double wt = std::fabs(A.A[0][0]) * (tx * p + 1) + std::fabs(A.A[0][1]) * (ty * p + 1);
-      const double ht = std::fabs(A.A[1][0]) * (tx * p + 1) + std::fabs(A.A[1][1]) * (ty * p + 1);
-      const int BW = ((int)std::floor(wt + 1e-6) + PW + 4 + 3) / 4 * 4;
-      const int BH = (int)std::floor(ht + 1e-6) + 1 + PH;
-      if ((long)BH * (BW / 4) > (long)BLOCK * var->NPF) continue;
-      const int ux = std::min(tx, w.n_sub_x), uy = std::min(ty, w.n_sub_y);
-      const double cost = (double)BW * BH / ((double)ux * uy);
-      if (cost < best) {
-        best = cost;
-        bt = tx;
-        bns = ns;
-        bBW = BW;
-        bBH = BH;
+    if (kVariants[i].PW >= pw_need && kVariants[i].PH() >= ph_need)
+      best_area = std::min(best_area, kVariants[i].PW * kVariants[i].PH());
+  if (best_area == INT_MAX) return 0;
+  const long n_sub = (long)w.n_sub_x * w.n_sub_y;
+  int n = 0;
+  for (int i = 0; i < kNumVariants; ++i) {
+    const Variant& v = kVariants[i];
+    if (v.PW * v.PH() != best_area || v.PW < pw_need || v.PH() < ph_need) continue;
+    const int nslot_max = v.BLOCK / v.LPS;
+    for (int ns = nslot_max; ns >= nslot_max / 4; ns /= 2)
+      for (int tx = 1; tx <= ns; tx *= 2) {
+        const int ty = ns / tx;
+        // a subaperture's patch origin is the floor of an affine function of
+        // (u*p, v*p), so over a tile the origins spread by at most these + 1
+        const double sx = std::fabs(A.A[0][0]) * p * (tx - 1) + std::fabs(A.A[0][1]) * p * (ty - 1);
+        const double sy = std::fabs(A.A[1][0]) * p * (tx - 1) + std::fabs(A.A[1][1]) * p * (ty - 1);
+        const int BW = ((int)std::floor(sx + 1e-6) + 1 + v.PW + 3 + 3) / 4 * 4;
+        const int BH = (int)std::floor(sy + 1e-6) + 1 + v.PH();
+        if ((long)BH * BW > v.cap_floats() || BH > MAX_TILE_ROWS) continue;
+        const int ux = std::min(tx, w.n_sub_x), uy = std::min(ty, w.n_sub_y);
+        const double fill = (double)(ux * uy) / ns;   // lanes with a subaperture
+        const long tiles = (long)((w.n_sub_x + tx - 1) / tx) * ((w.n_sub_y + ty - 1) / ty);
+        double cost = (double)(BW + 24) * BH / ((double)ux * uy) / fill;
+        if (tiles * 8 < 64 && n_sub > 64) cost *= 1.5;   // too few tiles to spread
+        Dims d{};
+        d.var = &v;
+        d.PH = v.PH();
+        d.PW = v.PW;
+        d.TX = tx;
+        d.TY = ty;
+        d.NSLOT = ns;
+        d.n_tiles_x = (w.n_sub_x + tx - 1) / tx;
+        d.n_tiles = (int)tiles;
+        d.BWmax = BW;
+        d.BHmax = BH;
+        // insertion into the cost-sorted output
+        int at = n;
+        while (at > 0 && cost_out[at - 1] > cost) --at;
+        if (at >= max_out) continue;
+        for (int k = std::min(n, max_out - 1); k > at; --k) {
+          out[k] = out[k - 1];
+          cost_out[k] = cost_out[k - 1];
+        }
+        out[at] = d;
+        cost_out[at] = cost;
+        if (n < max_out) ++n;
       }
-    }
   }
-  if (bt < 0) return SYNIM_E_UNSUPPORTED;
-  d->var = var;
-  d->PH = PH;
-  d->PW = PW;
-  d->TX = bt;
-  d->TY = bns / bt;
-  d->NSLOT = bns;
-  d->n_tiles_x = (w.n_sub_x + d->TX - 1) / d->TX;
-  d->n_tiles = d->n_tiles_x * ((w.n_sub_y + d->TY - 1) / d->TY);
-  d->BWmax = bBW;
-  d->BHmax = bBH;
-  d->S = bBW;
+  return n;
+}
+
+constexpr int MAX_CAND = 48;
+
+// Autotune cache: geometry key -> (variant, tile shape) measured fastest.
+struct TuneKey {
+  int n_sub_x, n_sub_y, p, n_valid;
+  long long a[4];   // the map's linear part, rounded to 1e-9
+  bool operator==(const TuneKey& o) const {
+    return n_sub_x == o.n_sub_x && n_sub_y == o.n_sub_y && p == o.p && n_valid == o.n_valid &&
+           a[0] == o.a[0] && a[1] == o.a[1] && a[2] == o.a[2] && a[3] == o.a[3];
+  }
+};
+struct TuneEntry {
+  TuneKey key;
+  int variant, TX, TY, NSLOT;
+};
+std::mutex g_tune_mu;
+TuneEntry g_tune[256];
+int g_tune_n = 0;
+
+TuneKey tune_key(const synim_wfs& w, const synim_affine& A) {
+  TuneKey k{w.n_sub_x, w.n_sub_y, w.p, w.n_valid, {}};
+  for (int i = 0; i < 4; ++i) k.a[i] = std::llround(A.A[i / 2][i % 2] * 1e9);
+  return k;
+}
+
+// The tuned configuration for this geometry if there is one, else the
+// cost model's first choice.
+int choose_dims(const synim_wfs& w, const synim_affine& A, Dims* d) {
+  Dims cand[MAX_CAND];
+  double cost[MAX_CAND];
+  const int n = candidate_dims(w, A, cand, cost, MAX_CAND);
+  if (n == 0) return SYNIM_E_UNSUPPORTED;
+  *d = cand[0];
+  const TuneKey key = tune_key(w, A);
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (int i = 0; i < g_tune_n; ++i)
+    if (g_tune[i].key == key)
+      for (int c = 0; c < n; ++c)
+        if (cand[c].var == &kVariants[g_tune[i].variant] && cand[c].TX == g_tune[i].TX &&
+            cand[c].TY == g_tune[i].TY && cand[c].NSLOT == g_tune[i].NSLOT) {
+          *d = cand[c];
+          return SYNIM_OK;
+        }
   return SYNIM_OK;
 }
 
@@ -494,11 +710,14 @@ WsLayout layout(const synim_wfs& w, const Dims& d, int planes) {
   };
   const size_t nv = (size_t)w.n_valid;
   L.status = take(16 * sizeof(int));
+  L.counters = take(8 * MAX_PLANES * sizeof(int));
+  L.scratch = take(64 * sizeof(float));
   L.origin = take(nv * sizeof(int2));
   L.inv2nk = take(nv * sizeof(double));
   L.weights = take((size_t)planes * nv * 2 * d.PH * d.PW * sizeof(float));
   L.slot_kk = take((size_t)d.n_tiles * d.NSLOT * sizeof(int));
-  L.bbox = take((size_t)d.n_tiles * sizeof(int4));
+  L.tile_info = take((size_t)d.n_tiles * sizeof(int4));
+  L.rows = take((size_t)d.n_tiles * d.BHmax * sizeof(int2));
   L.partials = take(planes > 1 ? (size_t)4 * GMAX_VJP * sizeof(double) : 0);
   L.total = off;
   return L;
@@ -509,18 +728,40 @@ struct Plan {
   WsLayout L;
   char* ws;
   int* status() const { return reinterpret_cast<int*>(ws + L.status); }
+  int* counters() const { return reinterpret_cast<int*>(ws + L.counters); }
+  float* scratch() const { return reinterpret_cast<float*>(ws + L.scratch); }
   int2* origin() const { return reinterpret_cast<int2*>(ws + L.origin); }
   double* inv2nk() const { return reinterpret_cast<double*>(ws + L.inv2nk); }
   float* weights() const { return reinterpret_cast<float*>(ws + L.weights); }
   int* slot_kk() const { return reinterpret_cast<int*>(ws + L.slot_kk); }
-  int4* bbox() const { return reinterpret_cast<int4*>(ws + L.bbox); }
+  int4* tile_info() const { return reinterpret_cast<int4*>(ws + L.tile_info); }
+  int2* rows() const { return reinterpret_cast<int2*>(ws + L.rows); }
   double* partials() const { return reinterpret_cast<double*>(ws + L.partials); }
 };
+
+// Largest workspace any candidate configuration of this geometry needs, so a
+// workspace sized once stays valid whatever the autotuner picks later.
+size_t max_layout(const synim_wfs& w, const synim_affine& A, int planes) {
+  Dims cand[MAX_CAND];
+  double cost[MAX_CAND];
+  const int n = candidate_dims(w, A, cand, cost, MAX_CAND);
+  size_t m = 0;
+  for (int i = 0; i < n; ++i) m = std::max(m, layout(w, cand[i], planes).total);
+  return m;
+}
+
+int build_plan_with(const synim_wfs& w, const synim_affine& A, const synim_affine* dA, int planes,
+                    void* ws, size_t ws_bytes, hipStream_t st, Plan* P);
 
 int build_plan(const synim_wfs& w, const synim_affine& A, const synim_affine* dA, int planes,
                void* ws, size_t ws_bytes, hipStream_t st, Plan* P) {
   int rc = choose_dims(w, A, &P->d);
   if (rc != SYNIM_OK) return rc;
+  return build_plan_with(w, A, dA, planes, ws, ws_bytes, st, P);
+}
+
+int build_plan_with(const synim_wfs& w, const synim_affine& A, const synim_affine* dA, int planes,
+                    void* ws, size_t ws_bytes, hipStream_t st, Plan* P) {
   P->L = layout(w, P->d, planes);
   if (!ws) return SYNIM_E_WORKSPACE;
   if (ws_bytes < P->L.total) return SYNIM_E_WORKSPACE;
@@ -536,7 +777,8 @@ int build_plan(const synim_wfs& w, const synim_affine& A, const synim_affine* dA
   if (planes > 1)
     for (int j = 0; j < 4; ++j) dm.m[j] = to_map(dA[j]);
 
-  SYNIM_HIP_TRY(hipMemsetAsync(P->status(), 0, 16 * sizeof(int), st));
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, P->status(), 16);
+  SYNIM_HIP_TRY(hipGetLastError());
   const int nv = w.n_valid;
   hipLaunchKernelGGL(plan_subaps_kernel, dim3((nv + 127) / 128), dim3(128), 0, st, m, w.valid_idx,
                      w.pupil, w.n_sub_x, w.p, nv, d.PH, d.PW, P->origin(), P->inv2nk(),
@@ -547,27 +789,58 @@ int build_plan(const synim_wfs& w, const synim_affine& A, const synim_affine* dA
                      m, inv, rx, ry, dm, planes, w.valid_idx, w.pupil, w.n_sub_x, w.p, nv, d.PH,
                      d.PW, P->origin(), P->inv2nk(), P->weights(), P->status());
   SYNIM_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(plan_tiles_kernel, dim3((d.n_tiles + 127) / 128), dim3(128), 0, st,
+  const long nslots = (long)d.n_tiles * d.NSLOT;
+  hipLaunchKernelGGL(plan_slots_kernel, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, st,
                      w.valid_idx, nv, w.n_sub_x, w.n_sub_y, d.TX, d.TY, d.n_tiles_x, d.n_tiles,
-                     P->origin(), d.PH, d.PW, d.BWmax, d.BHmax, P->slot_kk(), P->bbox(),
-                     P->status());
+                     P->slot_kk());
+  SYNIM_HIP_TRY(hipGetLastError());
+  hipLaunchKernelGGL(plan_rows_kernel, dim3(d.n_tiles), dim3(256), 0, st, d.NSLOT, P->slot_kk(),
+                     P->origin(), d.PH, d.PW, d.BHmax, d.var->cap_floats(), P->tile_info(),
+                     P->rows(), P->status());
   SYNIM_HIP_TRY(hipGetLastError());
   return SYNIM_OK;
 }
 
-int default_chunk(int n_act, int n_tiles) {
-  // aim for >= ~8 workgroups per CU (256 CUs) while keeping the per-workgroup
-  // weight load amortised over as many actuators as possible
-  const long target = 2048;
-  long chunks = (target + n_tiles - 1) / n_tiles;
-  int chunk = (int)std::max(1L, ((long)n_act + chunks - 1) / chunks);
-  return std::min(chunk, 64);
+// Resident workgroups of a stream kernel on the current device (cached).
+int persistent_grid(StreamFn fn, int block) {
+  struct Entry {
+    StreamFn fn;
+    int dev, grid;
+  };
+  static Entry cache[64];
+  static int n_cache = 0;
+  static std::mutex mu;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return -1;
+  std::lock_guard<std::mutex> lk(mu);
+  for (int i = 0; i < n_cache; ++i)
+    if (cache[i].fn == fn && cache[i].dev == dev) return cache[i].grid;
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return -1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(fn),
+                                                   block, 0) != hipSuccess)
+    return -1;
+  int grid = std::max(8, (cus * std::max(1, per_cu) + 7) / 8 * 8);
+  if (n_cache < 64) cache[n_cache++] = Entry{fn, dev, grid};
+  return grid;
 }
 
 int launch_stream(const Plan& P, const float* ifs, int n_act, int H_in, int W_in, int nv,
-                  int plane0, int nplanes, float* out, const float* grad, int chunk,
-                  hipStream_t st, int* grid_out = nullptr) {
+                  int plane0, int nplanes, float* out, const float* grad, hipStream_t st,
+                  int* grid_out = nullptr) {
   const Dims& d = P.d;
+  const Variant& v = *d.var;
+  const bool vec4 = (W_in % 4 == 0) && ((reinterpret_cast<uintptr_t>(ifs) & 15) == 0);
+  if ((long)H_in * W_in * 4 > INT_MAX) return SYNIM_E_SHAPE;   // 32-bit DMA offsets
+  StreamFn fn = grad ? (vec4 ? v.vjp4 : v.vjp1) : (vec4 ? v.im4 : v.im1);
+  const int G = persistent_grid(fn, v.BLOCK);
+  if (G < 0) return SYNIM_E_HIP;
+  if (grad && G > GMAX_VJP) return SYNIM_E_SHAPE;
+  // enough (chunk, tile) items per workgroup for dynamic balance, and chunks
+  // long enough to amortise each item's weight load
+  long chunk = ((long)n_act * d.n_tiles + 4L * G - 1) / (4L * G);
+  chunk = std::max(1L, std::min(64L, chunk));
   StreamArgs g{};
   g.ifs = ifs;
   g.n_act = n_act;
@@ -576,33 +849,26 @@ int launch_stream(const Plan& P, const float* ifs, int n_act, int H_in, int W_in
   g.origin = P.origin();
   g.weights = P.weights();
   g.slot_kk = P.slot_kk();
-  g.bbox = P.bbox();
+  g.tile_info = P.tile_info();
+  g.rows = P.rows();
+  g.BHmax = d.BHmax;
   g.nv = nv;
   g.n_tiles = d.n_tiles;
-  g.chunk = chunk;
-  g.n_chunks = (n_act + chunk - 1) / chunk;
   g.ns = d.NSLOT;
-  g.S = d.S;
-  g.BHmax = d.BHmax;
-  g.vec_ok = (W_in % 4 == 0) && ((reinterpret_cast<uintptr_t>(ifs) & 15) == 0);
+  g.chunk = (int)chunk;
+  g.n_chunks = (int)((n_act + chunk - 1) / chunk);
+  g.counters = P.counters();
+  g.scratch = P.scratch();
   g.plane0 = plane0;
   g.out_plane0 = plane0;
   g.out = out;
   g.grad = grad;
   g.partials = P.partials();
-  long total = (long)d.n_tiles * g.n_chunks;
-  long G = (total + 7) / 8 * 8;
-  if (G > INT_MAX) return SYNIM_E_SHAPE;
-  if (grad && G > GMAX_VJP) return SYNIM_E_SHAPE;
-  const size_t lds = (size_t)2 * d.BHmax * d.S * sizeof(float);
-  if (lds > 160 * 1024) return SYNIM_E_UNSUPPORTED;
-  StreamFn fn = grad ? d.var->vjp : d.var->im;
-  if (lds > 64 * 1024)
-    SYNIM_HIP_TRY(hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
-                                      hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  hipLaunchKernelGGL(fn, dim3((unsigned)G, 1, nplanes), dim3(BLOCK), lds, st, g);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, P.counters(), 8 * MAX_PLANES);
   SYNIM_HIP_TRY(hipGetLastError());
-  if (grid_out) *grid_out = (int)G;
+  hipLaunchKernelGGL(fn, dim3((unsigned)G, 1, nplanes), dim3(v.BLOCK), 0, st, g);
+  SYNIM_HIP_TRY(hipGetLastError());
+  if (grid_out) *grid_out = G;
   return SYNIM_OK;
 }
 
@@ -612,7 +878,7 @@ int check_common(const float* ifs, int n_act, int H_in, int W_in, const synim_af
   int rc = validate_wfs(wfs);
   if (rc != SYNIM_OK) return rc;
   if (n_act < 1 || H_in < 1 || W_in < 1) return SYNIM_E_SHAPE;
-  if ((long)H_in * W_in > (long)INT_MAX / 2) return SYNIM_E_SHAPE;
+  if ((long)H_in * W_in > (long)INT_MAX / 4) return SYNIM_E_SHAPE;
   return SYNIM_OK;
 }
 
@@ -627,11 +893,118 @@ extern "C" int synim_im_workspace(const synim_wfs* wfs, const synim_affine* A, i
   int rc = validate_wfs(wfs);
   if (rc != SYNIM_OK) return rc;
   if (planes != 1 && planes != 5) return SYNIM_E_PARAM;
+  const size_t m = max_layout(*wfs, *A, planes);
+  if (m == 0) return SYNIM_E_UNSUPPORTED;
+  *bytes = m;
+  return SYNIM_OK;
+}
+
+extern "C" int synim_im_autotune(const float* ifs, int n_act, int H_in, int W_in,
+                                 const synim_affine* A, const synim_wfs* wfs, float* im, void* ws,
+                                 size_t ws_bytes, int max_candidates, float* times_ms,
+                                 int* n_tried, void* stream) {
+  int rc = check_common(ifs, n_act, H_in, W_in, A, wfs);
+  if (rc != SYNIM_OK) return rc;
+  if (!im || !ws) return SYNIM_E_NULL;
+  if (max_candidates < 1) return SYNIM_E_PARAM;
+  hipStream_t st = (hipStream_t)stream;
+  Dims cand[MAX_CAND];
+  double cost[MAX_CAND];
+  const int n = std::min(max_candidates, candidate_dims(*wfs, *A, cand, cost, MAX_CAND));
+  if (n == 0) return SYNIM_E_UNSUPPORTED;
+  hipEvent_t e0, e1;
+  SYNIM_HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return SYNIM_E_HIP;
+  }
+  int best = -1;
+  float best_ms = 1e30f;
+  rc = SYNIM_OK;
+  for (int c = 0; c < n && rc == SYNIM_OK; ++c) {
+    Plan P{};
+    P.d = cand[c];
+    rc = build_plan_with(*wfs, *A, nullptr, 1, ws, ws_bytes, st, &P);
+    if (rc != SYNIM_OK) break;
+    rc = launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);   // warm
+    if (rc != SYNIM_OK) break;
+    const int reps = 3;
+    if (hipEventRecord(e0, st) != hipSuccess) { rc = SYNIM_E_HIP; break; }
+    for (int r = 0; r < reps && rc == SYNIM_OK; ++r)
+      rc = launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);
+    if (rc != SYNIM_OK) break;
+    float ms = 0.f;
+    if (hipEventRecord(e1, st) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+      rc = SYNIM_E_HIP;
+      break;
+    }
+    ms /= reps;
+    if (times_ms) times_ms[c] = ms;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != SYNIM_OK) return rc;
+  if (n_tried) *n_tried = n;
+  const TuneKey key = tune_key(*wfs, *A);
+  TuneEntry e{key, (int)(cand[best].var - kVariants), cand[best].TX, cand[best].TY,
+              cand[best].NSLOT};
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (int i = 0; i < g_tune_n; ++i)
+    if (g_tune[i].key == key) {
+      g_tune[i] = e;
+      return SYNIM_OK;
+    }
+  if (g_tune_n < 256) g_tune[g_tune_n++] = e;
+  return SYNIM_OK;
+}
+
+extern "C" int synim_im_config(const synim_wfs* wfs, const synim_affine* A, int* out7) {
+  if (!wfs || !A || !out7) return SYNIM_E_NULL;
+  int rc = validate_wfs(wfs);
+  if (rc != SYNIM_OK) return rc;
   Dims d{};
   rc = choose_dims(*wfs, *A, &d);
   if (rc != SYNIM_OK) return rc;
-  *bytes = layout(*wfs, d, planes).total;
+  out7[0] = d.var->BLOCK;
+  out7[1] = d.var->LPS;
+  out7[2] = d.PH;
+  out7[3] = d.PW;
+  out7[4] = d.TX;
+  out7[5] = d.TY;
+  out7[6] = d.var->NST;
   return SYNIM_OK;
+}
+
+extern "C" int synim_im_candidates(const synim_wfs* wfs, const synim_affine* A, int* out7,
+                                   int max_out, int* n_out) {
+  if (!wfs || !A || !out7 || !n_out) return SYNIM_E_NULL;
+  int rc = validate_wfs(wfs);
+  if (rc != SYNIM_OK) return rc;
+  Dims cand[MAX_CAND];
+  double cost[MAX_CAND];
+  const int n = std::min(max_out, candidate_dims(*wfs, *A, cand, cost, MAX_CAND));
+  for (int i = 0; i < n; ++i) {
+    int* o = out7 + 7 * i;
+    o[0] = cand[i].var->BLOCK;
+    o[1] = cand[i].var->LPS;
+    o[2] = cand[i].PH;
+    o[3] = cand[i].PW;
+    o[4] = cand[i].TX;
+    o[5] = cand[i].TY;
+    o[6] = cand[i].var->NST;
+  }
+  *n_out = n;
+  return SYNIM_OK;
+}
+
+extern "C" void synim_autotune_clear(void) {
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  g_tune_n = 0;
 }
 
 extern "C" int synim_im_build(const float* ifs, int n_act, int H_in, int W_in,
@@ -644,8 +1017,7 @@ extern "C" int synim_im_build(const float* ifs, int n_act, int H_in, int W_in,
   Plan P{};
   rc = build_plan(*wfs, *A, nullptr, 1, ws, ws_bytes, st, &P);
   if (rc != SYNIM_OK) return rc;
-  return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr,
-                       default_chunk(n_act, P.d.n_tiles), st);
+  return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);
 }
 
 extern "C" int synim_im_jacobian(const float* ifs, int n_act, int H_in, int W_in,
@@ -659,12 +1031,11 @@ extern "C" int synim_im_jacobian(const float* ifs, int n_act, int H_in, int W_in
   Plan P{};
   rc = build_plan(*wfs, *A, dA, 5, ws, ws_bytes, st, &P);
   if (rc != SYNIM_OK) return rc;
-  const int chunk = default_chunk(n_act, P.d.n_tiles);
   if (im) {
-    rc = launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, chunk, st);
+    rc = launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);
     if (rc != SYNIM_OK) return rc;
   }
-  return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 1, 4, dim, nullptr, chunk, st);
+  return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 1, 4, dim, nullptr, st);
 }
 
 extern "C" int synim_im_vjp(const float* ifs, int n_act, int H_in, int W_in,
@@ -678,12 +1049,8 @@ extern "C" int synim_im_vjp(const float* ifs, int n_act, int H_in, int W_in,
   Plan P{};
   rc = build_plan(*wfs, *A, dA, 5, ws, ws_bytes, st, &P);
   if (rc != SYNIM_OK) return rc;
-  // keep the grid within the partials buffer: grow the chunk if needed
-  int chunk = default_chunk(n_act, P.d.n_tiles);
-  while ((long)P.d.n_tiles * ((n_act + chunk - 1) / chunk) > GMAX_VJP - 8) chunk *= 2;
   int G = 0;
-  rc = launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 1, 4, nullptr, grad_im, chunk, st,
-                     &G);
+  rc = launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 1, 4, nullptr, grad_im, st, &G);
   if (rc != SYNIM_OK) return rc;
   hipLaunchKernelGGL(vjp_finalize_kernel, dim3(4), dim3(256), 0, st, P.partials(), G,
                      grad_theta);
@@ -717,7 +1084,7 @@ extern "C" int synim_im_apply(const float* ifs, int n_act, int H_in, int W_in,
   if (ws_bytes < P.L.total) return SYNIM_E_WORKSPACE;
   P.ws = static_cast<char*>(const_cast<void*>(ws));
   return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, plane, 1, out, nullptr,
-                       default_chunk(n_act, P.d.n_tiles), (hipStream_t)stream);
+                       (hipStream_t)stream);
 }
 
 extern "C" int synim_plan_status(const void* ws, int* host_out, void* stream) {
