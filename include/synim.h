@@ -235,6 +235,70 @@ void synim_autotune_clear(void);
  * and synchronises `stream`. */
 int synim_plan_status(const void* ws, int* host_out, void* stream);
 
+/* ------------------------------------------------------- multi-pair batch
+ * Every (WFS, DM) pair of a multi-WFS system (e.g. 6 LGS WFS x 3 DMs) built in
+ * one persistent launch - the multi-WFS batch of Sec. 4.2, where each DM's IF
+ * stack is fetched once for all the WFS that see it: pairs sharing a DM read
+ * each chunk of its stack side by side.  Pairs may have their own map (cone
+ * effect, off-axis footprint), WFS (uneven valid-subaperture counts) and DM
+ * (uneven actuator counts).  The maps live in device memory, so a graph
+ * captured by synim_batch_run_graph replays after synim_batch_set_maps
+ * without re-capture.  The kernel configuration is chosen at creation from
+ * the initial maps; later maps must not need larger weight patches or tiles
+ * (else synim_batch_status reports bits 0/1 and the affected slopes are
+ * missing - create a new batch). */
+
+typedef struct {
+  const float* ifs;           /* device [n_act][H_in][W_in]                     */
+  int32_t n_act, H_in, W_in;
+} synim_dm;
+
+typedef struct {
+  int32_t wfs, dm;            /* indices into the WFS and DM arrays             */
+  synim_affine A;             /* initial inverse map of the pair                */
+  float* im;                  /* device [dm.n_act][2 N(wfs)], IM layout above   */
+} synim_pair;
+
+typedef struct synim_batch synim_batch;   /* opaque, owned by the library */
+
+/* Workspace bytes for synim_batch_create (covers every kernel variant the
+ * batch autotuner may pick). */
+int synim_batch_workspace(const synim_wfs* wfs, int n_wfs, const synim_dm* dms, int n_dm,
+                          const synim_pair* pairs, int n_pairs, size_t* bytes);
+
+/* Build the batch's tables in `ws` (device, caller-owned, must outlive the
+ * batch) and upload the initial maps; *out receives the handle.  The WFS
+ * descriptors, DM stacks and outputs are borrowed.  Synchronises `stream`.
+ * Allocates only host-side bookkeeping and a small pinned staging buffer. */
+int synim_batch_create(const synim_wfs* wfs, int n_wfs, const synim_dm* dms, int n_dm,
+                       const synim_pair* pairs, int n_pairs, void* ws, size_t ws_bytes,
+                       void* stream, synim_batch** out);
+
+/* Upload new maps (host [n_pairs], pair order of creation) on `stream`. */
+int synim_batch_set_maps(synim_batch* b, const synim_affine* maps, void* stream);
+
+/* Enqueue the plans and the single stream launch of every pair. */
+int synim_batch_run(synim_batch* b, void* stream);
+
+/* As synim_batch_run, through a hipGraph captured on the first call (stream
+ * must not be NULL) and replayed afterwards. */
+int synim_batch_run_graph(synim_batch* b, void* stream);
+
+/* OR of the pairs' plan status words (see synim_plan_status); synchronises. */
+int synim_batch_status(synim_batch* b, int* host_out, void* stream);
+
+/* Time up to max_variants kernel variants on the batch (each pair with its
+ * best tile shape for that variant) and keep the fastest; drops a captured
+ * graph.  times_ms (host) and n_tried (host) may be NULL.  Synchronises. */
+int synim_batch_autotune(synim_batch* b, int max_variants, float* times_ms, int* n_tried,
+                         void* stream);
+
+/* out4 (host) = block size, lanes per subaperture, pipeline stages, grid. */
+int synim_batch_config(const synim_batch* b, int* out4);
+
+/* Release the handle (the workspace stays the caller's). */
+void synim_batch_destroy(synim_batch* b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -326,3 +326,95 @@ def plan_status(ws) -> int:
     _check(lib.synim_plan_status(ws.data_ptr(), C.byref(v), _stream_handle(ws.device)),
            "plan_status")
     return int(v.value)
+
+
+# --------------------------------------------------------------- multi-pair
+class Batch:
+    """Every (WFS, DM) pair of a multi-WFS system built in one persistent launch.
+
+    ``wfs``: list of :class:`Wfs`; ``stacks``: list of IF stacks (GPU float32
+    [n_act][H][W]); ``pairs``: list of (wfs index, dm index, map [2x3]).
+    ``outs[i]`` is pair i's IM [n_act(dm)][2 N(wfs)] (allocated if not given).
+    The maps stay in device memory: :meth:`set_maps` followed by
+    :meth:`run_graph` replays the captured graph without re-capture.
+    """
+
+    def __init__(self, wfs, stacks, pairs, outs=None, device="cuda"):
+        torch = _torch()
+        lib = load()
+        self._wfs = list(wfs)
+        self._stacks = [_dev_f32(t, "stack") for t in stacks]
+        self.n_pairs = len(pairs)
+        if outs is None:
+            outs = [torch.empty((self._stacks[d].shape[0], 2 * self._wfs[w].n_valid),
+                                dtype=torch.float32, device=device) for (w, d, _) in pairs]
+        self.outs = list(outs)
+        self._w = (_abi.SynimWfs * len(self._wfs))(*[w.struct() for w in self._wfs])
+        self._d = (_abi.SynimDm * len(self._stacks))(
+            *[_abi.SynimDm(t.data_ptr(), t.shape[0], t.shape[1], t.shape[2]) for t in self._stacks])
+        self._p = (_abi.SynimPair * self.n_pairs)(
+            *[_abi.SynimPair(w, d, _affine_struct(A), o.data_ptr())
+              for (w, d, A), o in zip(pairs, self.outs)])
+        n = C.c_size_t(0)
+        _check(lib.synim_batch_workspace(self._w, len(self._wfs), self._d, len(self._stacks),
+                                         self._p, self.n_pairs, C.byref(n)), "batch_workspace")
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device=device)
+        self._h = C.c_void_p(0)
+        self._stream = torch.cuda.current_stream(self.ws.device)
+        _check(lib.synim_batch_create(self._w, len(self._wfs), self._d, len(self._stacks),
+                                      self._p, self.n_pairs, self.ws.data_ptr(), self.ws.numel(),
+                                      self._stream.cuda_stream, C.byref(self._h)), "batch_create")
+
+    def _sh(self):
+        return _torch().cuda.current_stream(self.ws.device).cuda_stream
+
+    def set_maps(self, maps):
+        arr = (_abi.SynimAffine * self.n_pairs)(*[_affine_struct(A) for A in maps])
+        _check(load().synim_batch_set_maps(self._h, arr, self._sh()), "batch_set_maps")
+
+    def run(self):
+        _check(load().synim_batch_run(self._h, self._sh()), "batch_run")
+        return self.outs
+
+    def run_graph(self):
+        """Replay the captured graph (captured on the first call).
+
+        Graph capture needs a stream other than the null stream, so the graph
+        runs on a side stream of the batch, ordered after the caller's current
+        stream and before its later work."""
+        torch = _torch()
+        cur = torch.cuda.current_stream(self.ws.device)
+        if not hasattr(self, "_side"):
+            self._side = torch.cuda.Stream(device=self.ws.device)
+        self._side.wait_stream(cur)
+        _check(load().synim_batch_run_graph(self._h, self._side.cuda_stream), "batch_run_graph")
+        cur.wait_stream(self._side)
+        return self.outs
+
+    def status(self) -> int:
+        v = C.c_int(0)
+        _check(load().synim_batch_status(self._h, C.byref(v), self._sh()), "batch_status")
+        return int(v.value)
+
+    def autotune(self, max_variants: int = 6):
+        t = (C.c_float * max_variants)()
+        n = C.c_int(0)
+        _check(load().synim_batch_autotune(self._h, max_variants, t, C.byref(n), self._sh()),
+               "batch_autotune")
+        return [float(t[i]) for i in range(n.value)]
+
+    def config(self) -> dict:
+        o = (C.c_int * 4)()
+        _check(load().synim_batch_config(self._h, o), "batch_config")
+        return dict(block=o[0], lanes_per_subap=o[1], stages=o[2], grid=o[3])
+
+    def close(self):
+        if self._h and self._h.value:
+            load().synim_batch_destroy(self._h)
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

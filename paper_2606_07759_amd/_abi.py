@@ -28,6 +28,14 @@ class SynimWfs(C.Structure):
                 ("n_valid", C.c_int32), ("valid_idx", C.c_void_p), ("pupil", C.c_void_p)]
 
 
+class SynimDm(C.Structure):
+    _fields_ = [("ifs", C.c_void_p), ("n_act", C.c_int32), ("H_in", C.c_int32), ("W_in", C.c_int32)]
+
+
+class SynimPair(C.Structure):
+    _fields_ = [("wfs", C.c_int32), ("dm", C.c_int32), ("A", SynimAffine), ("im", C.c_void_p)]
+
+
 P = C.c_void_p
 I = C.c_int
 SZ = C.c_size_t
@@ -57,6 +65,17 @@ SIGNATURES = {
                               I, C.POINTER(C.c_float), C.POINTER(I), P]),
     "synim_im_config": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(I)]),
     "synim_autotune_clear": (None, []),
+    "synim_batch_workspace": (I, [C.POINTER(SynimWfs), I, C.POINTER(SynimDm), I,
+                                  C.POINTER(SynimPair), I, C.POINTER(SZ)]),
+    "synim_batch_create": (I, [C.POINTER(SynimWfs), I, C.POINTER(SynimDm), I,
+                               C.POINTER(SynimPair), I, P, SZ, P, C.POINTER(P)]),
+    "synim_batch_set_maps": (I, [P, C.POINTER(SynimAffine), P]),
+    "synim_batch_run": (I, [P, P]),
+    "synim_batch_run_graph": (I, [P, P]),
+    "synim_batch_status": (I, [P, C.POINTER(I), P]),
+    "synim_batch_autotune": (I, [P, I, C.POINTER(C.c_float), C.POINTER(I), P]),
+    "synim_batch_config": (I, [P, C.POINTER(I)]),
+    "synim_batch_destroy": (None, [P]),
     "synim_im_candidates": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(I), I,
                                 C.POINTER(I)]),
 }

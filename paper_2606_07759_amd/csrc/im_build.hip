@@ -31,6 +31,7 @@
 #include <cmath>
 #include <mutex>
 #include <utility>
+#include <vector>
 
 #include "common.hpp"
 
@@ -45,15 +46,47 @@ struct Map4 {
 
 // ------------------------------------------------------------------ planning
 
-__global__ void plan_subaps_kernel(MapD m, const int32_t* __restrict__ valid,
-                                   const uint8_t* __restrict__ pupil, int n_sub_x, int p, int nv,
-                                   int PH, int PW, int2* __restrict__ origin,
-                                   double* __restrict__ inv2nk, int* __restrict__ status) {
+constexpr int MAX_TILE_ROWS = 512;
+
+// Everything the plan kernels need for one (WFS, map) job.  Single builds
+// pass it by value; batches pass a device table indexed by blockIdx.y.  The
+// map (and the derivative maps) come by value, or from device memory when the
+// pointers are set, so a captured graph re-plans from whatever maps the
+// buffers hold at replay time.
+struct PlanJob {
+  MapD m;
+  Map4 dm;
+  const MapD* m_dev;          // overrides m when set
+  const Map4* dm_dev;         // overrides dm when set
+  const int32_t* valid;
+  const uint8_t* pupil;
+  int n_sub_x, n_sub_y, p, nv;
+  int PH, PW, n_planes, cap_floats;
+  int TX, TY, NSLOT, n_tiles_x;
+  int n_tiles, BHmax, pad0, pad1;
+  int2* origin;
+  double* inv2nk;
+  float* weights;             // [plane][kk][x|y][PH*PW]
+  int* slot_kk;               // [tile][NSLOT]
+  int4* tile_info;            // [tile] (y0, rows, packed floats, 0)
+  int2* rows;                 // [tile][BHmax] (first column, packed offset)
+  int* status;
+};
+
+__device__ __forceinline__ const PlanJob& job_of(const PlanJob& one, const PlanJob* jobs) {
+  return jobs ? jobs[blockIdx.y] : one;
+}
+
+// Origin (patch corner) and 1/(2 n_k) of each valid subaperture.
+__global__ void plan_subaps_kernel(PlanJob one, const PlanJob* __restrict__ jobs) {
+  const PlanJob& J = job_of(one, jobs);
   const int kk = blockIdx.x * blockDim.x + threadIdx.x;
-  if (kk >= nv) return;
-  const int k = valid[kk];
-  const int u = k % n_sub_x, v = k / n_sub_x;
-  const int W = n_sub_x * p;
+  if (kk >= J.nv) return;
+  const MapD m = J.m_dev ? *J.m_dev : J.m;
+  const int p = J.p;
+  const int k = J.valid[kk];
+  const int u = k % J.n_sub_x, v = k / J.n_sub_x;
+  const int W = J.n_sub_x * p;
   double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
   for (int y = v * p - 1; y <= v * p + p; ++y)
     for (int x = u * p - 1; x <= u * p + p; ++x) {
@@ -66,19 +99,20 @@ __global__ void plan_subaps_kernel(MapD m, const int32_t* __restrict__ valid,
     }
   int nk = 0;
   for (int y = v * p; y < v * p + p; ++y)
-    for (int x = u * p; x < u * p + p; ++x) nk += pupil[(size_t)y * W + x] ? 1 : 0;
+    for (int x = u * p; x < u * p + p; ++x) nk += J.pupil[(size_t)y * W + x] ? 1 : 0;
   int ox = 0, oy = 0;
   if (fabs(xmin) < 1e9 && fabs(xmax) < 1e9 && fabs(ymin) < 1e9 && fabs(ymax) < 1e9) {
     ox = (int)floor(xmin);
     oy = (int)floor(ymin);
     // the last tap column is floor(xmax) + 1
-    if ((int)floor(xmax) + 2 - ox > PW || (int)floor(ymax) + 2 - oy > PH) atomicOr(status, 1);
+    if ((int)floor(xmax) + 2 - ox > J.PW || (int)floor(ymax) + 2 - oy > J.PH)
+      atomicOr(J.status, 1);
   } else {
-    atomicOr(status, 1);
+    atomicOr(J.status, 1);
   }
-  if (nk == 0) atomicOr(status, 4);
-  origin[kk] = make_int2(ox, oy);
-  inv2nk[kk] = nk > 0 ? 1.0 / (2.0 * nk) : 0.0;
+  if (nk == 0) atomicOr(J.status, 4);
+  J.origin[kk] = make_int2(ox, oy);
+  J.inv2nk[kk] = nk > 0 ? 1.0 / (2.0 * nk) : 0.0;
 }
 
 __device__ __forceinline__ int in_sub(const uint8_t* __restrict__ pupil, int W, int x0, int y0,
@@ -89,22 +123,25 @@ __device__ __forceinline__ int in_sub(const uint8_t* __restrict__ pupil, int W, 
 // One thread per (valid subaperture, patch entry).  Gathers, in a fixed
 // order, every haloed-window sample q whose bilinear cell has this entry as a
 // tap.  Weights layout: [plane][kk][component x|y][PH*PW].
-__global__ void plan_weights_kernel(MapD m, MapD inv, double rx, double ry, Map4 dm, int n_planes,
-                                    const int32_t* __restrict__ valid,
-                                    const uint8_t* __restrict__ pupil, int n_sub_x, int p, int nv,
-                                    int PH, int PW, const int2* __restrict__ origin,
-                                    const double* __restrict__ inv2nk, float* __restrict__ weights,
-                                    int* __restrict__ status) {
-  const int E = PH * PW;
+__global__ void plan_weights_kernel(PlanJob one, const PlanJob* __restrict__ jobs) {
+  const PlanJob& J = job_of(one, jobs);
+  const int E = J.PH * J.PW;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long)nv * E) return;
+  if (gid >= (long)J.nv * E) return;
+  const MapD m = J.m_dev ? *J.m_dev : J.m;
+  const int p = J.p;
+  // inverse of the linear part, for the window of candidate samples
+  const double det = m.a00 * m.a11 - m.a01 * m.a10;
+  const MapD inv{m.a11 / det, -m.a01 / det, -m.a10 / det, m.a00 / det, 0, 0};
+  const double rx = fabs(inv.a00) + fabs(inv.a01) + 0.01;
+  const double ry = fabs(inv.a10) + fabs(inv.a11) + 0.01;
   const int kk = (int)(gid / E);
   const int e = (int)(gid - (long)kk * E);
-  const int r = e / PW, c = e - (e / PW) * PW;
-  const int k = valid[kk];
-  const int u = k % n_sub_x, v = k / n_sub_x;
-  const int W = n_sub_x * p;
-  const int2 o = origin[kk];
+  const int r = e / J.PW, c = e - (e / J.PW) * J.PW;
+  const int k = J.valid[kk];
+  const int u = k % J.n_sub_x, v = k / J.n_sub_x;
+  const int W = J.n_sub_x * p;
+  const int2 o = J.origin[kk];
   const int X = o.x + c, Y = o.y + r;
 
   // candidate window: p_o = A^-1 (p_s - b) with p_s in [X-1, X+1) x [Y-1, Y+1)
@@ -114,14 +151,16 @@ __global__ void plan_weights_kernel(MapD m, MapD inv, double rx, double ry, Map4
   const int xl = max(u * p - 1, (int)ceil(qx - rx)), xh = min(u * p + p, (int)floor(qx + rx));
   const int yl = max(v * p - 1, (int)ceil(qy - ry)), yh = min(v * p + p, (int)floor(qy + ry));
   const int sx0 = u * p, sy0 = v * p;
+  Map4 dm{};
+  if (J.n_planes > 1) dm = J.dm_dev ? *J.dm_dev : J.dm;
 
   double acc[5][2];
 #pragma unroll
   for (int j = 0; j < 5; ++j) acc[j][0] = acc[j][1] = 0.0;
   for (int y = yl; y <= yh; ++y)
     for (int x = xl; x <= xh; ++x) {
-      const int cx = in_sub(pupil, W, sx0, sy0, p, x - 1, y) - in_sub(pupil, W, sx0, sy0, p, x + 1, y);
-      const int cy = in_sub(pupil, W, sx0, sy0, p, x, y - 1) - in_sub(pupil, W, sx0, sy0, p, x, y + 1);
+      const int cx = in_sub(J.pupil, W, sx0, sy0, p, x - 1, y) - in_sub(J.pupil, W, sx0, sy0, p, x + 1, y);
+      const int cy = in_sub(J.pupil, W, sx0, sy0, p, x, y - 1) - in_sub(J.pupil, W, sx0, sy0, p, x, y + 1);
       if (cx == 0 && cy == 0) continue;
       double xs, ys;
       src_xy(m, x, y, xs, ys);
@@ -134,7 +173,7 @@ __global__ void plan_weights_kernel(MapD m, MapD inv, double rx, double ry, Map4
       const double w = wx * wy;
       acc[0][0] += cx * w;
       acc[0][1] += cy * w;
-      if (n_planes > 1) {
+      if (J.n_planes > 1) {
         // floor-cell gradient of the tap weight w.r.t. the source point
         const double dwa = (di == 0.0 ? -1.0 : 1.0) * wy;
         const double dwb = (dj == 0.0 ? -1.0 : 1.0) * wx;
@@ -148,13 +187,12 @@ __global__ void plan_weights_kernel(MapD m, MapD inv, double rx, double ry, Map4
         }
       }
     }
-  const double s = inv2nk[kk];
-  for (int j = 0; j < n_planes; ++j) {
-    float* w = weights + ((size_t)j * nv + kk) * 2 * E;
+  const double s = J.inv2nk[kk];
+  for (int j = 0; j < J.n_planes; ++j) {
+    float* w = J.weights + ((size_t)j * J.nv + kk) * 2 * E;
     w[e] = (float)(acc[j][0] * s);
     w[E + e] = (float)(acc[j][1] * s);
   }
-  (void)status;
 }
 
 __device__ int find_valid(const int32_t* __restrict__ valid, int nv, int k) {
@@ -169,55 +207,42 @@ __device__ int find_valid(const int32_t* __restrict__ valid, int nv, int k) {
 }
 
 // One thread per (tile, slot): which valid subaperture (if any) the slot holds.
-__global__ void plan_slots_kernel(const int32_t* __restrict__ valid, int nv, int n_sub_x,
-                                  int n_sub_y, int TX, int TY, int n_tiles_x, int n_tiles,
-                                  int* __restrict__ slot_kk) {
-  const int NS = TX * TY;
+__global__ void plan_slots_kernel(PlanJob one, const PlanJob* __restrict__ jobs) {
+  const PlanJob& J = job_of(one, jobs);
+  const int NS = J.TX * J.TY;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long)n_tiles * NS) return;
+  if (gid >= (long)J.n_tiles * NS) return;
   const int t = (int)(gid / NS), s = (int)(gid - (long)t * NS);
-  const int tu = t % n_tiles_x, tv = t / n_tiles_x;
-  const int u = tu * TX + s % TX, v = tv * TY + s / TX;
+  const int tu = t % J.n_tiles_x, tv = t / J.n_tiles_x;
+  const int u = tu * J.TX + s % J.TX, v = tv * J.TY + s / J.TX;
   int kk = -1;
-  if (u < n_sub_x && v < n_sub_y) kk = find_valid(valid, nv, v * n_sub_x + u);
-  slot_kk[gid] = kk;
+  if (u < J.n_sub_x && v < J.n_sub_y) kk = find_valid(J.valid, J.nv, v * J.n_sub_x + u);
+  J.slot_kk[gid] = kk;
 }
-
-__device__ __forceinline__ int wave_min(int v) {
-  for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
-  return v;
-}
-__device__ __forceinline__ int wave_max(int v) {
-  for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
-  return v;
-}
-
-constexpr int MAX_TILE_ROWS = 512;
 
 // One workgroup per tile: the IF rows its patches touch, each trimmed to the
 // column interval those patches cover (aligned to 4 floats), packed one after
 // the other.  tile_info[t] = (y0, rows, packed floats, 0), rows = 0 for an empty
 // tile; rows[t*BHmax + r] = (first column of row r, packed offset of row r).
-__global__ __launch_bounds__(256) void plan_rows_kernel(int NS, const int* __restrict__ slot_kk,
-                                                        const int2* __restrict__ origin, int PH,
-                                                        int PW, int BHmax, int cap_floats,
-                                                        int4* __restrict__ tile_info,
-                                                        int2* __restrict__ rows,
-                                                        int* __restrict__ status) {
+__global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
+                                                        const PlanJob* __restrict__ jobs) {
+  const PlanJob& J = job_of(one, jobs);
   __shared__ int s_ox[1024], s_oy[1024];
   __shared__ int s_x0[MAX_TILE_ROWS], s_w[MAX_TILE_ROWS];
   __shared__ int s_ymin, s_ymax;
   const int t = blockIdx.x, tid = threadIdx.x;
+  if (t >= J.n_tiles) return;
+  const int NS = J.NSLOT, PH = J.PH, PW = J.PW;
   if (tid == 0) {
     s_ymin = INT_MAX;
     s_ymax = INT_MIN;
   }
   __syncthreads();
   for (int s = tid; s < NS; s += blockDim.x) {
-    const int kk = slot_kk[(size_t)t * NS + s];
+    const int kk = J.slot_kk[(size_t)t * NS + s];
     int2 o = make_int2(INT_MIN, INT_MIN);
     if (kk >= 0) {
-      o = origin[kk];
+      o = J.origin[kk];
       atomicMin(&s_ymin, o.y);
       atomicMax(&s_ymax, o.y);
     }
@@ -227,14 +252,14 @@ __global__ __launch_bounds__(256) void plan_rows_kernel(int NS, const int* __res
   __syncthreads();
   const int y0 = s_ymin;
   if (y0 == INT_MAX) {
-    if (tid == 0) tile_info[t] = make_int4(0, 0, 0, 0);
+    if (tid == 0) J.tile_info[t] = make_int4(0, 0, 0, 0);
     return;
   }
   const int bh = s_ymax + PH - y0;
-  if (bh > BHmax || bh > MAX_TILE_ROWS) {
+  if (bh > J.BHmax || bh > MAX_TILE_ROWS) {
     if (tid == 0) {
-      atomicOr(status, 2);
-      tile_info[t] = make_int4(0, 0, 0, 0);
+      atomicOr(J.status, 2);
+      J.tile_info[t] = make_int4(0, 0, 0, 0);
     }
     return;
   }
@@ -261,14 +286,14 @@ __global__ __launch_bounds__(256) void plan_rows_kernel(int NS, const int* __res
   if (tid == 0) {
     int off = 0;
     for (int r = 0; r < bh; ++r) {
-      rows[(size_t)t * BHmax + r] = make_int2(s_x0[r], off);
+      J.rows[(size_t)t * J.BHmax + r] = make_int2(s_x0[r], off);
       off += s_w[r];
     }
-    if (off > cap_floats) {
-      atomicOr(status, 2);   // tile skipped: its slopes stay unwritten
-      tile_info[t] = make_int4(0, 0, 0, 0);
+    if (off > J.cap_floats) {
+      atomicOr(J.status, 2);   // tile skipped: its slopes stay unwritten
+      J.tile_info[t] = make_int4(0, 0, 0, 0);
     } else {
-      tile_info[t] = make_int4(y0, bh, off, 0);
+      J.tile_info[t] = make_int4(y0, bh, off, 0);
     }
   }
 }
@@ -276,6 +301,12 @@ __global__ __launch_bounds__(256) void plan_rows_kernel(int NS, const int* __res
 __global__ void zero_ints_kernel(int* __restrict__ p, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
+}
+
+__global__ void zero_job_status_kernel(const PlanJob* __restrict__ jobs, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n)
+    for (int k = 0; k < 16; ++k) jobs[i].status[k] = 0;
 }
 
 // ------------------------------------------------------------------ streaming
@@ -289,21 +320,41 @@ __device__ __forceinline__ float dpp_sum(float v, int lps) {
   return v;
 }
 
-struct StreamArgs {
-  const float* ifs;
-  int n_act, H_in, W_in;
+// One (WFS, DM) pair's planned build: its IF stack, its output and its plan.
+struct PairDesc {
+  const float* ifs;          // [n_act][H_in][W_in]
+  float* out;                // plane (out_plane0) of [plane][n_act][2nv]
   const int2* origin;
   const float* weights;      // plane 0 base
   const int* slot_kk;
   const int4* tile_info;
   const int2* rows;
-  int BHmax;
-  int nv, n_tiles, ns, chunk, n_chunks;
+  int n_act, H_in, W_in, nv;
+  int n_tiles, ns, BHmax, chunk;
+  int n_chunks, pad0, pad1, pad2;
+};
+
+// A batched launch walks "super-chunks": one actuator chunk of one DM, with
+// the tiles of every pair that sees that DM.  Super-chunks go round-robin to
+// the XCD queues, DM-major, so the pairs sharing a DM read each IF chunk at
+// about the same time on one XCD (the IF bytes come from HBM once).
+struct SuperChunk {
+  int item0;                 // first item of this record in its XCD's queue
+  int dm;                    // DM group
+  int chunk;                 // actuator chunk of that DM
+  int items;                 // sum of the tiles of the group's pairs
+};
+
+struct StreamArgs {
+  PairDesc one;              // single-pair launches
+  const PairDesc* pairs;     // batched launches: pair table (nullptr: single pair)
+  const SuperChunk* recs;    // batched: per-XCD records, XCD x at recs[rec_off[x]..]
+  const int2* groups;        // batched: per DM (first pair, number of pairs)
+  int rec_off[8], rec_cnt[8], xcd_items[8];
   int* counters;             // [gridDim.z][8] work counters, zeroed before the launch
   float* scratch;            // 64 floats that absorb the stores of idle lanes
   int plane0;                // first weight plane handled (blockIdx.z adds to it)
   int out_plane0;            // weight plane that lands in out[0]
-  float* out;                // [plane - out_plane0][n_act][2nv]
   const float* grad;         // VJP: [n_act][2nv]
   double* partials;          // VJP: [4][gridDim.x]
 };
@@ -381,11 +432,14 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
   const int slot = tid / LPS, q = tid % LPS;
   const int xcd = blockIdx.x & 7;
   const int plane = g.plane0 + blockIdx.z;
-  const int nc_x = g.n_chunks > xcd ? (g.n_chunks - xcd + 7) / 8 : 0;
-  const int n_items = nc_x * g.n_tiles;
+  int n_items;
+  if (g.pairs == nullptr) {
+    const int nc_x = g.one.n_chunks > xcd ? (g.one.n_chunks - xcd + 7) / 8 : 0;
+    n_items = nc_x * g.one.n_tiles;
+  } else {
+    n_items = g.xcd_items[xcd];
+  }
   int* ctr = g.counters + 8 * blockIdx.z + xcd;
-  const int plane_bytes = g.H_in * g.W_in * 4;
-  const size_t plane_in = (size_t)g.H_in * g.W_in;
   double vacc = 0.0;
 
   for (;;) {
@@ -394,20 +448,46 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
     __syncthreads();
     const int item = s_item;
     if (item >= n_items) break;
-    const int m = item / g.n_tiles;
-    const int tile = item - m * g.n_tiles;
-    const int chunk_id = xcd + 8 * m;
-    const int4 ti = g.tile_info[tile];
+    PairDesc P;
+    int tile, chunk_id;
+    if (g.pairs == nullptr) {
+      P = g.one;
+      const int m = item / P.n_tiles;
+      tile = item - m * P.n_tiles;
+      chunk_id = xcd + 8 * m;
+    } else {
+      // the record holding this item, then the pair within its DM group
+      const SuperChunk* rec = g.recs + g.rec_off[xcd];
+      int lo = 0, hi = g.rec_cnt[xcd] - 1;
+      while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (rec[mid].item0 <= item) lo = mid; else hi = mid - 1;
+      }
+      const SuperChunk r = rec[lo];
+      int local = item - r.item0;
+      const int2 grp = g.groups[r.dm];
+      int pi = grp.x;
+      while (pi < grp.x + grp.y - 1 && local >= g.pairs[pi].n_tiles) {
+        local -= g.pairs[pi].n_tiles;
+        ++pi;
+      }
+      P = g.pairs[pi];
+      tile = local;
+      chunk_id = r.chunk;
+    }
+    const int plane_bytes = P.H_in * P.W_in * 4;
+    const size_t plane_in = (size_t)P.H_in * P.W_in;
+    const int4 ti = P.tile_info[tile];
     if (ti.y == 0) continue;   // empty tile
     const int y0 = ti.x, nfl = ti.z;
-    const int kk = slot < g.ns ? g.slot_kk[(size_t)tile * g.ns + slot] : -1;
-    const int2* rows = g.rows + (size_t)tile * g.BHmax;
+    const int kk = slot < P.ns ? P.slot_kk[(size_t)tile * P.ns + slot] : -1;
+    const int2* rows = P.rows + (size_t)tile * P.BHmax;
 
     float wx[RPL][PW], wy[RPL][PW];
     int base[RPL];
     if (kk >= 0) {
-      const int2 o = g.origin[kk];
-      const float* W = g.weights + ((size_t)plane * g.nv + kk) * 2 * E;
+      const int2 o = P.origin[kk];
+      const float* W = P.weights + ((size_t)plane * P.nv + kk) * 2 * E;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
         const int2 rw = rows[o.y - y0 + q + LPS * i];
@@ -442,12 +522,12 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
         }
         const int2 rw = rows[lo];
         const int gx = rw.x + (fo - rw.y), gy = y0 + lo;
-        if (gx >= 0 && gx + VW <= g.W_in) v = (unsigned)(gy * g.W_in + gx) * 4u;
+        if (gx >= 0 && gx + VW <= P.W_in) v = (unsigned)(gy * P.W_in + gx) * 4u;
       }
       voff[j] = v;
     }
-    const int a0 = chunk_id * g.chunk;
-    const int a1 = min(g.n_act, a0 + g.chunk);
+    const int a0 = chunk_id * P.chunk;
+    const int a1 = min(P.n_act, a0 + P.chunk);
 
     auto consume = [&](const float4* buf, int a) {
       const float* fb = reinterpret_cast<const float*>(buf);
@@ -463,22 +543,22 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
       }
       sx = dpp_sum(sx, LPS);
       sy = dpp_sum(sy, LPS);
-      const size_t row = (size_t)a * 2 * g.nv;
+      const size_t row = (size_t)a * 2 * P.nv;
       if (VJP) {
         if (kk >= 0 && q == 0)
-          vacc += (double)g.grad[row + kk] * sx + (double)g.grad[row + g.nv + kk] * sy;
+          vacc += (double)g.grad[row + kk] * sx + (double)g.grad[row + P.nv + kk] * sy;
       } else {
         // exactly one store instruction per wave and actuator, whatever the
         // lanes hold: lanes with nothing to write target a scratch slot.  The
         // pipeline's wait counts rely on this number.
-        float* o = g.out + (size_t)(plane - g.out_plane0) * g.n_act * 2 * g.nv + row;
+        float* o = P.out + (size_t)(plane - g.out_plane0) * P.n_act * 2 * P.nv + row;
         const bool real = kk >= 0 && q < 2;
-        float* dst = real ? (q == 0 ? o + kk : o + g.nv + kk) : g.scratch + (tid & 63);
+        float* dst = real ? (q == 0 ? o + kk : o + P.nv + kk) : g.scratch + (tid & 63);
         __builtin_nontemporal_store(q == 0 ? sx : sy, dst);
       }
     };
     auto issue = [&](float4* buf, int a) {
-      stage_issue<BLOCK, NJ, VW>(g.ifs + (size_t)a * plane_in, plane_bytes, voff, buf, wave);
+      stage_issue<BLOCK, NJ, VW>(P.ifs + (size_t)a * plane_in, plane_bytes, voff, buf, wave);
     };
     // one pipeline step for actuator a held in stage K: wait for it (the later
     // stages already issued may stay in flight), make it visible to every
@@ -590,66 +670,98 @@ struct WsLayout {
 
 constexpr int MAX_PLANES = 5;
 
-// Every (variant, tile shape) that can run this geometry, cheapest first by the
-// cost model: the smallest weight patch that fits, then staged IF floats per
-// subaperture (a partial 128-byte line counted at each row end), for tiles
-// whose packed rows provably fit the stage buffers.
-int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double* cost_out,
-                   int max_out) {
+// Patch size (columns, rows) a map needs for subapertures of p pixels: the
+// haloed subaperture spans (p+1) output pixels, which the map stretches by
+// the row sums of |A|; a bilinear tap adds one more column/row.
+void patch_need(const synim_affine& A, int p, int* pw, int* ph) {
   const double ax = std::fabs(A.A[0][0]) + std::fabs(A.A[0][1]);
   const double ay = std::fabs(A.A[1][0]) + std::fabs(A.A[1][1]);
+  *pw = (int)std::floor(ax * (p + 1) + 1e-7) + 3;
+  *ph = (int)std::floor(ay * (p + 1) + 1e-7) + 3;
+}
+
+// Tile shapes of one variant for this geometry, cheapest first by the cost
+// model: staged IF floats per subaperture (a partial 128-byte line counted at
+// each row end), for tiles whose packed rows provably fit the stage buffers.
+int tiles_for_variant(const synim_wfs& w, const synim_affine& A, const Variant& v, Dims* out,
+                      double* cost_out, int max_out) {
+  int pw_need, ph_need;
+  patch_need(A, w.p, &pw_need, &ph_need);
+  if (v.PW < pw_need || v.PH() < ph_need) return 0;
   const int p = w.p;
-  const int pw_need = (int)std::floor(ax * (p + 1) + 1e-7) + 3;
-  const int ph_need = (int)std::floor(ay * (p + 1) + 1e-7) + 3;
+  const long n_sub = (long)w.n_sub_x * w.n_sub_y;
+  int n = 0;
+  const int nslot_max = v.BLOCK / v.LPS;
+  for (int ns = nslot_max; ns >= nslot_max / 4; ns /= 2)
+    for (int tx = 1; tx <= ns; tx *= 2) {
+      const int ty = ns / tx;
+      // a subaperture's patch origin is the floor of an affine function of
+      // (u*p, v*p), so over a tile the origins spread by at most these + 1
+      const double sx = std::fabs(A.A[0][0]) * p * (tx - 1) + std::fabs(A.A[0][1]) * p * (ty - 1);
+      const double sy = std::fabs(A.A[1][0]) * p * (tx - 1) + std::fabs(A.A[1][1]) * p * (ty - 1);
+      const int BW = ((int)std::floor(sx + 1e-6) + 1 + v.PW + 3 + 3) / 4 * 4;
+      const int BH = (int)std::floor(sy + 1e-6) + 1 + v.PH();
+      if ((long)BH * BW > v.cap_floats() || BH > MAX_TILE_ROWS) continue;
+      const int ux = std::min(tx, w.n_sub_x), uy = std::min(ty, w.n_sub_y);
+      const double fill = (double)(ux * uy) / ns;   // lanes with a subaperture
+      const long tiles = (long)((w.n_sub_x + tx - 1) / tx) * ((w.n_sub_y + ty - 1) / ty);
+      double cost = (double)(BW + 24) * BH / ((double)ux * uy) / fill;
+      if (tiles * 8 < 64 && n_sub > 64) cost *= 1.5;   // too few tiles to spread
+      Dims d{};
+      d.var = &v;
+      d.PH = v.PH();
+      d.PW = v.PW;
+      d.TX = tx;
+      d.TY = ty;
+      d.NSLOT = ns;
+      d.n_tiles_x = (w.n_sub_x + tx - 1) / tx;
+      d.n_tiles = (int)tiles;
+      d.BWmax = BW;
+      d.BHmax = BH;
+      int at = n;
+      while (at > 0 && cost_out[at - 1] > cost) --at;
+      if (at >= max_out) continue;
+      for (int k = std::min(n, max_out - 1); k > at; --k) {
+        out[k] = out[k - 1];
+        cost_out[k] = cost_out[k - 1];
+      }
+      out[at] = d;
+      cost_out[at] = cost;
+      if (n < max_out) ++n;
+    }
+  return n;
+}
+
+// Every (variant, tile shape) that can run this geometry with the smallest
+// weight patch that fits, cheapest first by the cost model.
+int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double* cost_out,
+                   int max_out) {
+  int pw_need, ph_need;
+  patch_need(A, w.p, &pw_need, &ph_need);
   int best_area = INT_MAX;
   for (int i = 0; i < kNumVariants; ++i)
     if (kVariants[i].PW >= pw_need && kVariants[i].PH() >= ph_need)
       best_area = std::min(best_area, kVariants[i].PW * kVariants[i].PH());
   if (best_area == INT_MAX) return 0;
-  const long n_sub = (long)w.n_sub_x * w.n_sub_y;
   int n = 0;
   for (int i = 0; i < kNumVariants; ++i) {
     const Variant& v = kVariants[i];
-    if (v.PW * v.PH() != best_area || v.PW < pw_need || v.PH() < ph_need) continue;
-    const int nslot_max = v.BLOCK / v.LPS;
-    for (int ns = nslot_max; ns >= nslot_max / 4; ns /= 2)
-      for (int tx = 1; tx <= ns; tx *= 2) {
-        const int ty = ns / tx;
-        // a subaperture's patch origin is the floor of an affine function of
-        // (u*p, v*p), so over a tile the origins spread by at most these + 1
-        const double sx = std::fabs(A.A[0][0]) * p * (tx - 1) + std::fabs(A.A[0][1]) * p * (ty - 1);
-        const double sy = std::fabs(A.A[1][0]) * p * (tx - 1) + std::fabs(A.A[1][1]) * p * (ty - 1);
-        const int BW = ((int)std::floor(sx + 1e-6) + 1 + v.PW + 3 + 3) / 4 * 4;
-        const int BH = (int)std::floor(sy + 1e-6) + 1 + v.PH();
-        if ((long)BH * BW > v.cap_floats() || BH > MAX_TILE_ROWS) continue;
-        const int ux = std::min(tx, w.n_sub_x), uy = std::min(ty, w.n_sub_y);
-        const double fill = (double)(ux * uy) / ns;   // lanes with a subaperture
-        const long tiles = (long)((w.n_sub_x + tx - 1) / tx) * ((w.n_sub_y + ty - 1) / ty);
-        double cost = (double)(BW + 24) * BH / ((double)ux * uy) / fill;
-        if (tiles * 8 < 64 && n_sub > 64) cost *= 1.5;   // too few tiles to spread
-        Dims d{};
-        d.var = &v;
-        d.PH = v.PH();
-        d.PW = v.PW;
-        d.TX = tx;
-        d.TY = ty;
-        d.NSLOT = ns;
-        d.n_tiles_x = (w.n_sub_x + tx - 1) / tx;
-        d.n_tiles = (int)tiles;
-        d.BWmax = BW;
-        d.BHmax = BH;
-        // insertion into the cost-sorted output
-        int at = n;
-        while (at > 0 && cost_out[at - 1] > cost) --at;
-        if (at >= max_out) continue;
-        for (int k = std::min(n, max_out - 1); k > at; --k) {
-          out[k] = out[k - 1];
-          cost_out[k] = cost_out[k - 1];
-        }
-        out[at] = d;
-        cost_out[at] = cost;
-        if (n < max_out) ++n;
+    if (v.PW * v.PH() != best_area) continue;
+    Dims tmp[64];
+    double tc[64];
+    const int m = tiles_for_variant(w, A, v, tmp, tc, 64);
+    for (int k = 0; k < m; ++k) {
+      int at = n;
+      while (at > 0 && cost_out[at - 1] > tc[k]) --at;
+      if (at >= max_out) continue;
+      for (int j = std::min(n, max_out - 1); j > at; --j) {
+        out[j] = out[j - 1];
+        cost_out[j] = cost_out[j - 1];
       }
+      out[at] = tmp[k];
+      cost_out[at] = tc[k];
+      if (n < max_out) ++n;
+    }
   }
   return n;
 }
@@ -752,6 +864,8 @@ size_t max_layout(const synim_wfs& w, const synim_affine& A, int planes) {
 
 int build_plan_with(const synim_wfs& w, const synim_affine& A, const synim_affine* dA, int planes,
                     void* ws, size_t ws_bytes, hipStream_t st, Plan* P);
+int enqueue_plan(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map4& dm, int planes,
+                 const Plan& P, hipStream_t st);
 
 int build_plan(const synim_wfs& w, const synim_affine& A, const synim_affine* dA, int planes,
                void* ws, size_t ws_bytes, hipStream_t st, Plan* P) {
@@ -770,35 +884,81 @@ int build_plan_with(const synim_wfs& w, const synim_affine& A, const synim_affin
   const MapD m = to_map(A);
   const double det = m.a00 * m.a11 - m.a01 * m.a10;
   if (!(std::fabs(det) > 1e-12)) return SYNIM_E_PARAM;
-  MapD inv{m.a11 / det, -m.a01 / det, -m.a10 / det, m.a00 / det, 0, 0};
-  const double rx = std::fabs(inv.a00) + std::fabs(inv.a01) + 0.01;
-  const double ry = std::fabs(inv.a10) + std::fabs(inv.a11) + 0.01;
   Map4 dm{};
   if (planes > 1)
     for (int j = 0; j < 4; ++j) dm.m[j] = to_map(dA[j]);
+  return enqueue_plan(w, m, nullptr, dm, planes, *P, st);
+}
 
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, P->status(), 16);
+// The plan job of one pair: its WFS, plan regions and kernel dimensions.
+PlanJob make_job(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map4& dm,
+                 const Map4* dm_dev, int planes, const Plan& P) {
+  const Dims& d = P.d;
+  PlanJob J{};
+  J.m = m;
+  J.dm = dm;
+  J.m_dev = m_dev;
+  J.dm_dev = dm_dev;
+  J.valid = w.valid_idx;
+  J.pupil = w.pupil;
+  J.n_sub_x = w.n_sub_x;
+  J.n_sub_y = w.n_sub_y;
+  J.p = w.p;
+  J.nv = w.n_valid;
+  J.PH = d.PH;
+  J.PW = d.PW;
+  J.n_planes = planes;
+  J.cap_floats = d.var->cap_floats();
+  J.TX = d.TX;
+  J.TY = d.TY;
+  J.NSLOT = d.NSLOT;
+  J.n_tiles_x = d.n_tiles_x;
+  J.n_tiles = d.n_tiles;
+  J.BHmax = d.BHmax;
+  J.origin = P.origin();
+  J.inv2nk = P.inv2nk();
+  J.weights = P.weights();
+  J.slot_kk = P.slot_kk();
+  J.tile_info = P.tile_info();
+  J.rows = P.rows();
+  J.status = P.status();
+  return J;
+}
+
+// Enqueue the plan kernels for `n` jobs: one job by value (jobs_dev null) or
+// a device table of n jobs (maxima give the grid extents).
+int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv, int max_e,
+                  int max_slots, int max_tiles, hipStream_t st) {
+  if (jobs_dev) {
+    hipLaunchKernelGGL(zero_job_status_kernel, dim3((n + 255) / 256), dim3(256), 0, st, jobs_dev,
+                       n);
+  } else {
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, one.status, 16);
+  }
   SYNIM_HIP_TRY(hipGetLastError());
-  const int nv = w.n_valid;
-  hipLaunchKernelGGL(plan_subaps_kernel, dim3((nv + 127) / 128), dim3(128), 0, st, m, w.valid_idx,
-                     w.pupil, w.n_sub_x, w.p, nv, d.PH, d.PW, P->origin(), P->inv2nk(),
-                     P->status());
-  SYNIM_HIP_TRY(hipGetLastError());
-  const long nthr = (long)nv * d.PH * d.PW;
-  hipLaunchKernelGGL(plan_weights_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, st,
-                     m, inv, rx, ry, dm, planes, w.valid_idx, w.pupil, w.n_sub_x, w.p, nv, d.PH,
-                     d.PW, P->origin(), P->inv2nk(), P->weights(), P->status());
-  SYNIM_HIP_TRY(hipGetLastError());
-  const long nslots = (long)d.n_tiles * d.NSLOT;
-  hipLaunchKernelGGL(plan_slots_kernel, dim3((unsigned)((nslots + 255) / 256)), dim3(256), 0, st,
-                     w.valid_idx, nv, w.n_sub_x, w.n_sub_y, d.TX, d.TY, d.n_tiles_x, d.n_tiles,
-                     P->slot_kk());
-  SYNIM_HIP_TRY(hipGetLastError());
-  hipLaunchKernelGGL(plan_rows_kernel, dim3(d.n_tiles), dim3(256), 0, st, d.NSLOT, P->slot_kk(),
-                     P->origin(), d.PH, d.PW, d.BHmax, d.var->cap_floats(), P->tile_info(),
-                     P->rows(), P->status());
-  SYNIM_HIP_TRY(hipGetLastError());
+  for (int j0 = 0; j0 < n; j0 += 65535) {
+    const int nj = std::min(65535, n - j0);
+    const PlanJob* jt = jobs_dev ? jobs_dev + j0 : nullptr;
+    hipLaunchKernelGGL(plan_subaps_kernel, dim3((max_nv + 127) / 128, nj), dim3(128), 0, st, one,
+                       jt);
+    SYNIM_HIP_TRY(hipGetLastError());
+    const long nthr = (long)max_nv * max_e;
+    hipLaunchKernelGGL(plan_weights_kernel, dim3((unsigned)((nthr + 255) / 256), nj), dim3(256),
+                       0, st, one, jt);
+    SYNIM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(plan_slots_kernel, dim3((unsigned)((max_slots + 255) / 256), nj),
+                       dim3(256), 0, st, one, jt);
+    SYNIM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(plan_rows_kernel, dim3(max_tiles, nj), dim3(256), 0, st, one, jt);
+    SYNIM_HIP_TRY(hipGetLastError());
+  }
   return SYNIM_OK;
+}
+
+int enqueue_plan(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map4& dm, int planes,
+                 const Plan& P, hipStream_t st) {
+  const PlanJob J = make_job(w, m, m_dev, dm, nullptr, planes, P);
+  return enqueue_plans(J, nullptr, 1, J.nv, J.PH * J.PW, J.n_tiles * J.NSLOT, J.n_tiles, st);
 }
 
 // Resident workgroups of a stream kernel on the current device (cached).
@@ -826,6 +986,39 @@ int persistent_grid(StreamFn fn, int block) {
   return grid;
 }
 
+// Chunk length: enough (chunk, tile) items per workgroup for dynamic balance,
+// and chunks long enough to amortise each item's weight load.
+int chunk_for(long act_tiles, int G) {
+  long chunk = (act_tiles + 4L * G - 1) / (4L * G);
+  return (int)std::max(1L, std::min(64L, chunk));
+}
+
+StreamFn pick_fn(const Variant& v, bool vec4, bool vjp) {
+  return vjp ? (vec4 ? v.vjp4 : v.vjp1) : (vec4 ? v.im4 : v.im1);
+}
+
+PairDesc pair_desc(const Plan& P, const float* ifs, int n_act, int H_in, int W_in, int nv,
+                   float* out, int chunk) {
+  PairDesc pd{};
+  pd.ifs = ifs;
+  pd.out = out;
+  pd.origin = P.origin();
+  pd.weights = P.weights();
+  pd.slot_kk = P.slot_kk();
+  pd.tile_info = P.tile_info();
+  pd.rows = P.rows();
+  pd.n_act = n_act;
+  pd.H_in = H_in;
+  pd.W_in = W_in;
+  pd.nv = nv;
+  pd.n_tiles = P.d.n_tiles;
+  pd.ns = P.d.NSLOT;
+  pd.BHmax = P.d.BHmax;
+  pd.chunk = chunk;
+  pd.n_chunks = (n_act + chunk - 1) / chunk;
+  return pd;
+}
+
 int launch_stream(const Plan& P, const float* ifs, int n_act, int H_in, int W_in, int nv,
                   int plane0, int nplanes, float* out, const float* grad, hipStream_t st,
                   int* grid_out = nullptr) {
@@ -833,35 +1026,18 @@ int launch_stream(const Plan& P, const float* ifs, int n_act, int H_in, int W_in
   const Variant& v = *d.var;
   const bool vec4 = (W_in % 4 == 0) && ((reinterpret_cast<uintptr_t>(ifs) & 15) == 0);
   if ((long)H_in * W_in * 4 > INT_MAX) return SYNIM_E_SHAPE;   // 32-bit DMA offsets
-  StreamFn fn = grad ? (vec4 ? v.vjp4 : v.vjp1) : (vec4 ? v.im4 : v.im1);
+  StreamFn fn = pick_fn(v, vec4, grad != nullptr);
   const int G = persistent_grid(fn, v.BLOCK);
   if (G < 0) return SYNIM_E_HIP;
   if (grad && G > GMAX_VJP) return SYNIM_E_SHAPE;
-  // enough (chunk, tile) items per workgroup for dynamic balance, and chunks
-  // long enough to amortise each item's weight load
-  long chunk = ((long)n_act * d.n_tiles + 4L * G - 1) / (4L * G);
-  chunk = std::max(1L, std::min(64L, chunk));
   StreamArgs g{};
-  g.ifs = ifs;
-  g.n_act = n_act;
-  g.H_in = H_in;
-  g.W_in = W_in;
-  g.origin = P.origin();
-  g.weights = P.weights();
-  g.slot_kk = P.slot_kk();
-  g.tile_info = P.tile_info();
-  g.rows = P.rows();
-  g.BHmax = d.BHmax;
-  g.nv = nv;
-  g.n_tiles = d.n_tiles;
-  g.ns = d.NSLOT;
-  g.chunk = (int)chunk;
-  g.n_chunks = (int)((n_act + chunk - 1) / chunk);
+  g.one = pair_desc(P, ifs, n_act, H_in, W_in, nv, out,
+                    chunk_for((long)n_act * d.n_tiles, G));
+  g.pairs = nullptr;
   g.counters = P.counters();
   g.scratch = P.scratch();
   g.plane0 = plane0;
   g.out_plane0 = plane0;
-  g.out = out;
   g.grad = grad;
   g.partials = P.partials();
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, P.counters(), 8 * MAX_PLANES);
@@ -1093,4 +1269,436 @@ extern "C" int synim_plan_status(const void* ws, int* host_out, void* stream) {
                                (hipStream_t)stream));
   SYNIM_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   return SYNIM_OK;
+}
+
+// ------------------------------------------------------------------- batches
+//
+// Every (WFS, DM) pair of a multi-WFS system in one persistent launch (the
+// paper's multi-WFS batch, Sec. 4.2): the pairs share one kernel variant, each
+// pair keeps its own plan and tile shape, and DM-major super-chunks make the
+// pairs that see a DM read each chunk of its IF stack side by side on one XCD.
+// The maps live in device memory, so a captured graph replays after
+// synim_batch_set_maps without re-capture.
+
+struct synim_batch {
+  std::vector<synim_wfs> wfs;
+  std::vector<synim_dm> dms;
+  std::vector<synim_pair> pairs;
+  std::vector<int> order;        // pair indices sorted by DM
+  const Variant* var = nullptr;
+  std::vector<Plan> plans;       // per pair (original index)
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  size_t off_maps = 0, off_pairs = 0, off_recs = 0, off_groups = 0, off_ctr = 0, off_scratch = 0;
+  size_t off_jobs = 0;
+  int max_nv = 0, max_e = 0, max_slots = 0, max_tiles = 0;
+  int n_recs = 0;
+  int rec_off[8] = {}, rec_cnt[8] = {}, xcd_items[8] = {};
+  int G = 0;
+  bool vec4 = true;
+  MapD* staging = nullptr;       // pinned host copy of the maps
+  hipEvent_t staged = nullptr;   // the last upload from `staging` has been read
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace synim {
+namespace {
+
+// The batch's tables and the pairs' plans for kernel variant v, laid out in
+// the workspace; returns the bytes needed (layout only if b->ws is null).
+int batch_layout(synim_batch* b, const Variant& v, size_t* bytes) {
+  const int np = (int)b->pairs.size();
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    size_t at = off;
+    off = align_up(off + n, 256);
+    return at;
+  };
+  b->off_maps = take(np * sizeof(MapD));
+  b->off_jobs = take(np * sizeof(PlanJob));
+  b->off_pairs = take(np * sizeof(PairDesc));
+  b->off_groups = take(b->dms.size() * sizeof(int2));
+  b->off_ctr = take(8 * sizeof(int));
+  b->off_scratch = take(64 * sizeof(float));
+  // upper bound on the records: every DM chunk of length 1
+  long max_recs = 0;
+  for (const auto& d : b->dms) max_recs += d.n_act;
+  b->off_recs = take(max_recs * sizeof(SuperChunk));
+  b->plans.assign(np, Plan{});
+  for (int i = 0; i < np; ++i) {
+    const synim_pair& pr = b->pairs[i];
+    const synim_wfs& w = b->wfs[pr.wfs];
+    Dims cand[64];
+    double cost[64];
+    if (tiles_for_variant(w, pr.A, v, cand, cost, 64) == 0) return SYNIM_E_UNSUPPORTED;
+    Plan& P = b->plans[i];
+    P.d = cand[0];
+    P.L = layout(w, P.d, 1);
+    const size_t at = take(P.L.total);
+    P.ws = reinterpret_cast<char*>(at);   // offset until the workspace is bound
+  }
+  *bytes = off;
+  return SYNIM_OK;
+}
+
+// Kernel variant for a batch: the smallest patch every pair fits, then the
+// variant whose best tiles cost least summed over the pairs.
+const Variant* batch_variant(const synim_batch* b, int rank) {
+  int area_best = INT_MAX;
+  for (int i = 0; i < kNumVariants; ++i) {
+    bool ok = true;
+    for (const auto& pr : b->pairs) {
+      int pw, ph;
+      patch_need(pr.A, b->wfs[pr.wfs].p, &pw, &ph);
+      if (kVariants[i].PW < pw || kVariants[i].PH() < ph) ok = false;
+    }
+    if (ok) area_best = std::min(area_best, kVariants[i].PW * kVariants[i].PH());
+  }
+  if (area_best == INT_MAX) return nullptr;
+  std::vector<std::pair<double, int>> ranked;
+  for (int i = 0; i < kNumVariants; ++i) {
+    const Variant& v = kVariants[i];
+    if (v.PW * v.PH() != area_best) continue;
+    double total = 0;
+    bool ok = true;
+    for (const auto& pr : b->pairs) {
+      Dims c[64];
+      double cost[64];
+      if (tiles_for_variant(b->wfs[pr.wfs], pr.A, v, c, cost, 64) == 0) {
+        ok = false;
+        break;
+      }
+      total += cost[0] * b->wfs[pr.wfs].n_valid;
+    }
+    if (ok) ranked.push_back({total, i});
+  }
+  std::sort(ranked.begin(), ranked.end());
+  if (rank >= (int)ranked.size()) return nullptr;
+  return &kVariants[ranked[rank].second];
+}
+
+// Bind the layout of variant v to the workspace and upload the tables.
+int batch_bind(synim_batch* b, const Variant& v, hipStream_t st) {
+  size_t need = 0;
+  int rc = batch_layout(b, v, &need);
+  if (rc != SYNIM_OK) return rc;
+  if (need > b->ws_bytes) return SYNIM_E_WORKSPACE;
+  b->var = &v;
+  const int np = (int)b->pairs.size();
+  for (auto& P : b->plans) P.ws = b->ws + reinterpret_cast<size_t>(P.ws);
+  b->vec4 = true;
+  for (const auto& d : b->dms)
+    if (d.W_in % 4 != 0 || (reinterpret_cast<uintptr_t>(d.ifs) & 15) != 0) b->vec4 = false;
+  StreamFn fn = pick_fn(v, b->vec4, false);
+  b->G = persistent_grid(fn, v.BLOCK);
+  if (b->G < 0) return SYNIM_E_HIP;
+  long act_tiles = 0;
+  for (int i = 0; i < np; ++i)
+    act_tiles += (long)b->dms[b->pairs[i].dm].n_act * b->plans[i].d.n_tiles;
+  const int chunk = chunk_for(act_tiles, b->G);
+  // pair table in DM order, groups, super-chunk records
+  std::vector<PairDesc> pd(np);
+  std::vector<int2> groups(b->dms.size(), make_int2(0, 0));
+  int at = 0;
+  for (int d = 0; d < (int)b->dms.size(); ++d) {
+    groups[d] = make_int2(at, 0);
+    for (int i : b->order)
+      if (b->pairs[i].dm == d) {
+        const synim_dm& dm = b->dms[d];
+        pd[at++] = pair_desc(b->plans[i], dm.ifs, dm.n_act, dm.H_in, dm.W_in,
+                             b->wfs[b->pairs[i].wfs].n_valid, b->pairs[i].im, chunk);
+        groups[d].y++;
+      }
+  }
+  std::vector<std::vector<SuperChunk>> per(8);
+  long sc = 0;
+  for (int d = 0; d < (int)b->dms.size(); ++d) {
+    if (groups[d].y == 0) continue;
+    int items = 0;
+    for (int k = 0; k < groups[d].y; ++k) items += pd[groups[d].x + k].n_tiles;
+    const int nch = (b->dms[d].n_act + chunk - 1) / chunk;
+    for (int c = 0; c < nch; ++c, ++sc) {
+      const int x = (int)(sc % 8);
+      per[x].push_back(SuperChunk{0, d, c, items});
+    }
+  }
+  std::vector<SuperChunk> recs;
+  for (int x = 0; x < 8; ++x) {
+    b->rec_off[x] = (int)recs.size();
+    b->rec_cnt[x] = (int)per[x].size();
+    int acc = 0;
+    for (auto r : per[x]) {
+      r.item0 = acc;
+      acc += r.items;
+      recs.push_back(r);
+    }
+    b->xcd_items[x] = acc;
+  }
+  b->n_recs = (int)recs.size();
+  std::vector<PlanJob> jobs(np);
+  const MapD* maps_dev = reinterpret_cast<const MapD*>(b->ws + b->off_maps);
+  b->max_nv = b->max_e = b->max_slots = b->max_tiles = 0;
+  for (int i = 0; i < np; ++i) {
+    const synim_pair& pr = b->pairs[i];
+    jobs[i] = make_job(b->wfs[pr.wfs], to_map(pr.A), maps_dev + i, Map4{}, nullptr, 1,
+                       b->plans[i]);
+    b->max_nv = std::max(b->max_nv, jobs[i].nv);
+    b->max_e = std::max(b->max_e, jobs[i].PH * jobs[i].PW);
+    b->max_slots = std::max(b->max_slots, jobs[i].n_tiles * jobs[i].NSLOT);
+    b->max_tiles = std::max(b->max_tiles, jobs[i].n_tiles);
+  }
+  SYNIM_HIP_TRY(hipMemcpyAsync(b->ws + b->off_jobs, jobs.data(), np * sizeof(PlanJob),
+                               hipMemcpyHostToDevice, st));
+  SYNIM_HIP_TRY(hipMemcpyAsync(b->ws + b->off_pairs, pd.data(), np * sizeof(PairDesc),
+                               hipMemcpyHostToDevice, st));
+  SYNIM_HIP_TRY(hipMemcpyAsync(b->ws + b->off_groups, groups.data(), groups.size() * sizeof(int2),
+                               hipMemcpyHostToDevice, st));
+  if (!recs.empty())
+    SYNIM_HIP_TRY(hipMemcpyAsync(b->ws + b->off_recs, recs.data(),
+                                 recs.size() * sizeof(SuperChunk), hipMemcpyHostToDevice, st));
+  SYNIM_HIP_TRY(hipStreamSynchronize(st));   // the host vectors go out of scope
+  return SYNIM_OK;
+}
+
+int batch_enqueue(synim_batch* b, hipStream_t st) {
+  const int np = (int)b->pairs.size();
+  int rc = enqueue_plans(PlanJob{}, reinterpret_cast<const PlanJob*>(b->ws + b->off_jobs), np,
+                         b->max_nv, b->max_e, b->max_slots, b->max_tiles, st);
+  if (rc != SYNIM_OK) return rc;
+  StreamArgs g{};
+  g.pairs = reinterpret_cast<const PairDesc*>(b->ws + b->off_pairs);
+  g.recs = reinterpret_cast<const SuperChunk*>(b->ws + b->off_recs);
+  g.groups = reinterpret_cast<const int2*>(b->ws + b->off_groups);
+  for (int x = 0; x < 8; ++x) {
+    g.rec_off[x] = b->rec_off[x];
+    g.rec_cnt[x] = b->rec_cnt[x];
+    g.xcd_items[x] = b->xcd_items[x];
+  }
+  g.counters = reinterpret_cast<int*>(b->ws + b->off_ctr);
+  g.scratch = reinterpret_cast<float*>(b->ws + b->off_scratch);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, g.counters, 8);
+  SYNIM_HIP_TRY(hipGetLastError());
+  StreamFn fn = pick_fn(*b->var, b->vec4, false);
+  hipLaunchKernelGGL(fn, dim3((unsigned)b->G, 1, 1), dim3(b->var->BLOCK), 0, st, g);
+  SYNIM_HIP_TRY(hipGetLastError());
+  return SYNIM_OK;
+}
+
+void batch_drop_graph(synim_batch* b) {
+  if (b->exec) (void)hipGraphExecDestroy(b->exec);
+  if (b->graph) (void)hipGraphDestroy(b->graph);
+  b->exec = nullptr;
+  b->graph = nullptr;
+}
+
+int batch_check(const synim_wfs* wfs, int n_wfs, const synim_dm* dms, int n_dm,
+                const synim_pair* pairs, int n_pairs) {
+  if (!wfs || !dms || !pairs) return SYNIM_E_NULL;
+  if (n_wfs < 1 || n_dm < 1 || n_pairs < 1) return SYNIM_E_SHAPE;
+  for (int i = 0; i < n_wfs; ++i) {
+    int rc = validate_wfs(&wfs[i]);
+    if (rc != SYNIM_OK) return rc;
+  }
+  for (int i = 0; i < n_dm; ++i) {
+    if (!dms[i].ifs) return SYNIM_E_NULL;
+    if (dms[i].n_act < 1 || dms[i].H_in < 1 || dms[i].W_in < 1) return SYNIM_E_SHAPE;
+    if ((long)dms[i].H_in * dms[i].W_in * 4 > INT_MAX) return SYNIM_E_SHAPE;
+  }
+  for (int i = 0; i < n_pairs; ++i) {
+    if (!pairs[i].im) return SYNIM_E_NULL;
+    if (pairs[i].wfs < 0 || pairs[i].wfs >= n_wfs || pairs[i].dm < 0 || pairs[i].dm >= n_dm)
+      return SYNIM_E_SHAPE;
+  }
+  return SYNIM_OK;
+}
+
+void batch_fill(synim_batch* b, const synim_wfs* wfs, int n_wfs, const synim_dm* dms, int n_dm,
+                const synim_pair* pairs, int n_pairs) {
+  b->wfs.assign(wfs, wfs + n_wfs);
+  b->dms.assign(dms, dms + n_dm);
+  b->pairs.assign(pairs, pairs + n_pairs);
+  b->order.resize(n_pairs);
+  for (int i = 0; i < n_pairs; ++i) b->order[i] = i;
+  std::stable_sort(b->order.begin(), b->order.end(),
+                   [&](int x, int y) { return pairs[x].dm < pairs[y].dm; });
+}
+
+}  // namespace
+}  // namespace synim
+
+extern "C" int synim_batch_workspace(const synim_wfs* wfs, int n_wfs, const synim_dm* dms,
+                                     int n_dm, const synim_pair* pairs, int n_pairs,
+                                     size_t* bytes) {
+  if (!bytes) return SYNIM_E_NULL;
+  int rc = batch_check(wfs, n_wfs, dms, n_dm, pairs, n_pairs);
+  if (rc != SYNIM_OK) return rc;
+  synim_batch b;
+  batch_fill(&b, wfs, n_wfs, dms, n_dm, pairs, n_pairs);
+  size_t m = 0;
+  for (int r = 0;; ++r) {
+    const Variant* v = batch_variant(&b, r);
+    if (!v) break;
+    size_t need = 0;
+    if (batch_layout(&b, *v, &need) == SYNIM_OK) m = std::max(m, need);
+  }
+  if (m == 0) return SYNIM_E_UNSUPPORTED;
+  *bytes = m;
+  return SYNIM_OK;
+}
+
+extern "C" int synim_batch_create(const synim_wfs* wfs, int n_wfs, const synim_dm* dms, int n_dm,
+                                  const synim_pair* pairs, int n_pairs, void* ws, size_t ws_bytes,
+                                  void* stream, synim_batch** out) {
+  if (!out || !ws) return SYNIM_E_NULL;
+  *out = nullptr;
+  int rc = batch_check(wfs, n_wfs, dms, n_dm, pairs, n_pairs);
+  if (rc != SYNIM_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  synim_batch* b = new synim_batch;
+  batch_fill(b, wfs, n_wfs, dms, n_dm, pairs, n_pairs);
+  b->ws = static_cast<char*>(ws);
+  b->ws_bytes = ws_bytes;
+  const Variant* v = batch_variant(b, 0);
+  rc = v ? batch_bind(b, *v, st) : SYNIM_E_UNSUPPORTED;
+  if (rc == SYNIM_OK && hipHostMalloc(reinterpret_cast<void**>(&b->staging),
+                                      n_pairs * sizeof(MapD), hipHostMallocDefault) != hipSuccess)
+    rc = SYNIM_E_HIP;
+  if (rc == SYNIM_OK && hipEventCreateWithFlags(&b->staged, hipEventDisableTiming) != hipSuccess)
+    rc = SYNIM_E_HIP;
+  if (rc == SYNIM_OK) {
+    std::vector<synim_affine> a(n_pairs);
+    for (int i = 0; i < n_pairs; ++i) a[i] = pairs[i].A;
+    rc = synim_batch_set_maps(b, a.data(), stream);
+  }
+  if (rc != SYNIM_OK) {
+    synim_batch_destroy(b);
+    return rc;
+  }
+  *out = b;
+  return SYNIM_OK;
+}
+
+extern "C" int synim_batch_set_maps(synim_batch* b, const synim_affine* maps, void* stream) {
+  if (!b || !maps) return SYNIM_E_NULL;
+  hipStream_t st = (hipStream_t)stream;
+  const int np = (int)b->pairs.size();
+  // the previous upload must have left the staging buffer before it is reused
+  SYNIM_HIP_TRY(hipEventSynchronize(b->staged));
+  for (int i = 0; i < np; ++i) {
+    const double det = maps[i].A[0][0] * maps[i].A[1][1] - maps[i].A[0][1] * maps[i].A[1][0];
+    if (!(std::fabs(det) > 1e-12)) return SYNIM_E_PARAM;
+    b->staging[i] = to_map(maps[i]);
+  }
+  SYNIM_HIP_TRY(hipMemcpyAsync(b->ws + b->off_maps, b->staging, np * sizeof(MapD),
+                               hipMemcpyHostToDevice, st));
+  SYNIM_HIP_TRY(hipEventRecord(b->staged, st));
+  return SYNIM_OK;
+}
+
+extern "C" int synim_batch_run(synim_batch* b, void* stream) {
+  if (!b) return SYNIM_E_NULL;
+  return batch_enqueue(b, (hipStream_t)stream);
+}
+
+extern "C" int synim_batch_run_graph(synim_batch* b, void* stream) {
+  if (!b) return SYNIM_E_NULL;
+  if (!stream) return SYNIM_E_PARAM;   // capture needs an explicit stream
+  hipStream_t st = (hipStream_t)stream;
+  if (!b->exec) {
+    SYNIM_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int rc = batch_enqueue(b, st);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &g);
+    if (rc != SYNIM_OK || e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc != SYNIM_OK ? rc : SYNIM_E_HIP;
+    }
+    b->graph = g;
+    if (hipGraphInstantiate(&b->exec, g, nullptr, nullptr, 0) != hipSuccess) {
+      batch_drop_graph(b);
+      return SYNIM_E_HIP;
+    }
+  }
+  SYNIM_HIP_TRY(hipGraphLaunch(b->exec, st));
+  return SYNIM_OK;
+}
+
+extern "C" int synim_batch_status(synim_batch* b, int* host_out, void* stream) {
+  if (!b || !host_out) return SYNIM_E_NULL;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int> s(b->plans.size(), 0);
+  for (size_t i = 0; i < b->plans.size(); ++i)
+    SYNIM_HIP_TRY(hipMemcpyAsync(&s[i], b->plans[i].status(), sizeof(int), hipMemcpyDeviceToHost,
+                                 st));
+  SYNIM_HIP_TRY(hipStreamSynchronize(st));
+  int v = 0;
+  for (int x : s) v |= x;
+  *host_out = v;
+  return SYNIM_OK;
+}
+
+extern "C" int synim_batch_autotune(synim_batch* b, int max_variants, float* times_ms,
+                                    int* n_tried, void* stream) {
+  if (!b) return SYNIM_E_NULL;
+  if (max_variants < 1) return SYNIM_E_PARAM;
+  hipStream_t st = (hipStream_t)stream;
+  batch_drop_graph(b);
+  hipEvent_t e0, e1;
+  SYNIM_HIP_TRY(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return SYNIM_E_HIP;
+  }
+  int best = -1, tried = 0, rc = SYNIM_OK;
+  float best_ms = 1e30f;
+  for (int r = 0; r < max_variants && rc == SYNIM_OK; ++r) {
+    const Variant* v = batch_variant(b, r);
+    if (!v) break;
+    if (batch_bind(b, *v, st) != SYNIM_OK) continue;   // does not fit this workspace
+    rc = batch_enqueue(b, st);
+    if (rc != SYNIM_OK) break;
+    const int reps = 3;
+    if (hipEventRecord(e0, st) != hipSuccess) { rc = SYNIM_E_HIP; break; }
+    for (int k = 0; k < reps && rc == SYNIM_OK; ++k) rc = batch_enqueue(b, st);
+    float ms = 0.f;
+    if (rc == SYNIM_OK && (hipEventRecord(e1, st) != hipSuccess ||
+                           hipEventSynchronize(e1) != hipSuccess ||
+                           hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+      rc = SYNIM_E_HIP;
+    if (rc != SYNIM_OK) break;
+    ms /= reps;
+    if (times_ms) times_ms[tried] = ms;
+    ++tried;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = r;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (rc != SYNIM_OK) return rc;
+  if (n_tried) *n_tried = tried;
+  if (best < 0) return SYNIM_E_UNSUPPORTED;
+  return batch_bind(b, *batch_variant(b, best), st);
+}
+
+extern "C" int synim_batch_config(const synim_batch* b, int* out4) {
+  if (!b || !out4 || !b->var) return SYNIM_E_NULL;
+  out4[0] = b->var->BLOCK;
+  out4[1] = b->var->LPS;
+  out4[2] = b->var->NST;
+  out4[3] = b->G;
+  return SYNIM_OK;
+}
+
+extern "C" void synim_batch_destroy(synim_batch* b) {
+  if (!b) return;
+  batch_drop_graph(b);
+  if (b->staged) {
+    (void)hipEventSynchronize(b->staged);
+    (void)hipEventDestroy(b->staged);
+  }
+  if (b->staging) (void)hipHostFree(b->staging);
+  delete b;
 }
