@@ -299,6 +299,100 @@ int synim_batch_config(const synim_batch* b, int* out4);
 /* Release the handle (the workspace stays the caller's). */
 void synim_batch_destroy(synim_batch* b);
 
+/* --------------------------------------------------- learned estimator
+ * A small MLP x (n_in) -> h1 -> h2 -> n_out (ReLU after the hidden layers),
+ * trained with an MSE loss and Adam, for the learned misregistration
+ * estimate.  Parameters are one packed FP32 buffer
+ *   W1 [h1][n_in], b1 [h1], W2 [h2][h1], b2 [h2], W3 [n_out][h2], b3 [n_out].
+ * Inputs are compact: the non-zero inputs of the input layer lie in two column
+ * segments, so x is [B][len0 + len1] and compact column c feeds input
+ * seg0 + c (c < len0) or seg1 + c - len0; every other input is zero. */
+typedef struct {
+  int32_t n_in, h1, h2, n_out;
+  int32_t seg0, len0, seg1, len1;
+} synim_mlp;
+
+/* Number of packed parameters (0 for an invalid description). */
+size_t synim_mlp_param_count(const synim_mlp* net);
+/* Floats of caller scratch needed for a batch of B (activations kept from the
+ * forward pass for the backward pass). */
+size_t synim_mlp_scratch_floats(const synim_mlp* net, int B);
+
+/* y [B][n_out] = net(x [B][len0+len1]); scratch keeps the activations. */
+int synim_mlp_forward(const synim_mlp* net, const float* params, const float* x, int B,
+                      float* scratch, float* y, void* stream);
+
+/* Gradients of mean((y - t)^2) after synim_mlp_forward on the same x and
+ * scratch; grads is packed like params and fully overwritten (W1 columns
+ * outside the segments get 0); loss (device float, nullable). */
+int synim_mlp_backward(const synim_mlp* net, const float* params, const float* x, int B,
+                       float* scratch, const float* y, const float* t, float* grads,
+                       float* loss, void* stream);
+
+/* One Adam step (bias-corrected, step >= 1) over n parameters, in place. */
+int synim_adam_step(float* params, const float* grads, float* m, float* v, size_t n, int step,
+                    float lr, float beta1, float beta2, float eps, void* stream);
+
+/* ---------------------------------------------- misregistration estimation
+ * Online tracking regenerates IMs from misregistration estimates (Sec. 5).
+ * theta = (shift_x px, shift_y px, rot rad, mag) is estimated from measured
+ * slopes of n_probe probe phase maps (e.g. Zernike modes fitted by the DM):
+ *   S(theta) = slopes of the probes through the map of theta (as
+ *              synim_im_build, one row of 2N per probe), J = dS/dtheta;
+ *   Gauss-Newton theta <- theta + (J^T J)^-1 J^T (s - S(theta)) from
+ *              theta0 = (0, 0, 0, 1), converged when |step / half-range| < tol;
+ *   learned:   a synim_mlp (n_in = 2*feat_len -> h1 -> h2 -> 4) on the
+ *              standardised features [x slopes | y slopes] (probe-major,
+ *              subaperture-minor, each channel zero-padded to feat_len) whose
+ *              output y in [-1, 1] maps to lo + (y + 1)(hi - lo)/2.
+ * A call handles up to max_batch samples, each its own map, in one multi-pair
+ * build per iteration; the loop runs on the device with no host sync. */
+
+#define SYNIM_MISREG_GN 0
+#define SYNIM_MISREG_MLP 1
+#define SYNIM_MISREG_MLP_GN 2
+
+typedef struct {
+  synim_wfs wfs;              /* the WFS (device arrays)                        */
+  const float* probes;        /* device [n_probe][H_in][W_in] probe phase maps  */
+  int32_t n_probe, H_in, W_in;
+  double kappa;               /* IF pixels per WFS pixel                        */
+  int32_t max_batch;          /* samples per call, 1..65535                     */
+  double theta_lo[4], theta_hi[4];   /* label box; plans are sized for it       */
+  int32_t max_iter;           /* Gauss-Newton iterations, 1..100                */
+  double tol;
+  const float* mlp_params;    /* device packed MLP, or NULL (GN only)           */
+  int32_t h1, h2, feat_len;   /* hidden sizes; per-channel input length         */
+  const float* feat_mean;     /* device [2 n_probe N] feature mean              */
+  const float* feat_std;      /* device [2 n_probe N] feature std (> 0)         */
+} synim_misreg_desc;
+
+typedef struct synim_misreg_ctx synim_misreg_ctx;
+
+int synim_misreg_workspace(const synim_misreg_desc* d, size_t* bytes);
+/* Borrows the probes, WFS arrays, MLP and feature statistics; synchronises. */
+int synim_misreg_create(const synim_misreg_desc* d, void* ws, size_t ws_bytes, void* stream,
+                        synim_misreg_ctx** out);
+/* Probe slopes S (device [B][n_probe*2N]) and, if jac is not NULL, the
+ * Jacobian (device [B][4][n_probe*2N]) at theta (device float64 [B][4]). */
+int synim_misreg_slopes(synim_misreg_ctx* c, const double* theta, int B, float* slopes,
+                        float* jac, void* stream);
+/* Features (device [B][2 n_probe N], compact MLP input) of slopes; standardised
+ * with mean/std (device, nullable: raw features). */
+int synim_misreg_features(synim_misreg_ctx* c, const float* slopes, int B, const float* mean,
+                          const float* std, float* x, void* stream);
+/* Estimate theta (device float64 [B][4]) from slopes (device [B][n_probe*2N]).
+ * mode: SYNIM_MISREG_GN, _MLP, _MLP_GN (GN started from the MLP estimate).
+ * iters (device int32 [B], nullable): GN steps taken (0 for MLP).  iter_cap
+ * (<= max_iter, 0 = max_iter) bounds the GN loop.  use_graph: replay a graph
+ * captured per (B, mode, iter_cap) on `stream` (must not be NULL). */
+int synim_misreg_infer(synim_misreg_ctx* c, const float* slopes, int B, int mode, double* theta,
+                       int32_t* iters, int iter_cap, int use_graph, void* stream);
+/* OR of the plan status words of the last GN run's plans (see
+ * synim_plan_status); synchronises. */
+int synim_misreg_status(synim_misreg_ctx* c, int* host_out, void* stream);
+void synim_misreg_destroy(synim_misreg_ctx* c);
+
 #ifdef __cplusplus
 }
 #endif

@@ -418,3 +418,166 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ------------------------------------------------------------------ MLP
+class Mlp:
+    """Packed-parameter MLP n_in -> h1 -> h2 -> n_out (HIP forward/backward/Adam).
+
+    ``segments`` = ((seg0, len0), (seg1, len1)): compact input column c feeds
+    input seg0 + c (c < len0) or seg1 + c - len0; all other inputs are zero."""
+
+    def __init__(self, n_in, h1, h2, n_out, segments):
+        (s0, l0), (s1, l1) = segments
+        self.desc = _abi.SynimMlp(n_in, h1, h2, n_out, s0, l0, s1, l1)
+        self.n_params = int(load().synim_mlp_param_count(C.byref(self.desc)))
+        if self.n_params == 0:
+            raise ValueError("invalid MLP description")
+
+    @property
+    def n_compact(self) -> int:
+        return self.desc.len0 + self.desc.len1
+
+    def layout(self):
+        d = self.desc
+        sizes = [d.h1 * d.n_in, d.h1, d.h2 * d.h1, d.h2, d.n_out * d.h2, d.n_out]
+        offs = np.cumsum([0] + sizes)
+        return [(int(offs[i]), int(offs[i + 1])) for i in range(6)]
+
+    def scratch(self, B, device="cuda"):
+        torch = _torch()
+        n = int(load().synim_mlp_scratch_floats(C.byref(self.desc), B))
+        return torch.empty(n, dtype=torch.float32, device=device)
+
+    def forward(self, params, x, scratch, out=None):
+        torch = _torch()
+        _dev_f32(params, "params")
+        _dev_f32(x, "x")
+        B = x.shape[0]
+        if out is None:
+            out = torch.empty((B, self.desc.n_out), dtype=torch.float32, device=x.device)
+        _check(load().synim_mlp_forward(C.byref(self.desc), params.data_ptr(), x.data_ptr(), B,
+                                        scratch.data_ptr(), out.data_ptr(),
+                                        _stream_handle(x.device)), "mlp_forward")
+        return out
+
+    def backward(self, params, x, scratch, y, t, grads, loss=None):
+        _check(load().synim_mlp_backward(C.byref(self.desc), params.data_ptr(), x.data_ptr(),
+                                         x.shape[0], scratch.data_ptr(), y.data_ptr(),
+                                         t.data_ptr(), grads.data_ptr(),
+                                         loss.data_ptr() if loss is not None else None,
+                                         _stream_handle(x.device)), "mlp_backward")
+        return grads
+
+
+def adam_step(params, grads, m, v, step, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):
+    _check(load().synim_adam_step(params.data_ptr(), grads.data_ptr(), m.data_ptr(),
+                                  v.data_ptr(), params.numel(), int(step), float(lr),
+                                  float(beta1), float(beta2), float(eps),
+                                  _stream_handle(params.device)), "adam_step")
+
+
+# ------------------------------------------------------- misregistration
+MISREG_GN, MISREG_MLP, MISREG_MLP_GN = 0, 1, 2
+
+
+class Misreg:
+    """Batched misregistration estimation from probe slopes (GN, MLP, MLP+GN).
+
+    ``probes``: GPU float32 [n_probe][H][W] probe phase maps; ``wfs``:
+    :class:`Wfs`; ``lo``/``hi``: label box (shift x px, shift y px, rot rad,
+    mag).  ``mlp`` = (Mlp, params, feat_mean, feat_std, feat_len) or None."""
+
+    def __init__(self, wfs: Wfs, probes, lo, hi, max_batch=1, max_iter=20, tol=1e-7,
+                 kappa=1.0, mlp=None):
+        torch = _torch()
+        lib = load()
+        self.wfs = wfs
+        self.probes = _dev_f32(probes, "probes")
+        self.mlp = mlp
+        d = _abi.SynimMisregDesc()
+        d.wfs = wfs.struct()
+        d.probes = probes.data_ptr()
+        d.n_probe, d.H_in, d.W_in = probes.shape
+        d.kappa = float(kappa)
+        d.max_batch = int(max_batch)
+        for j in range(4):
+            d.theta_lo[j] = float(lo[j])
+            d.theta_hi[j] = float(hi[j])
+        d.max_iter = int(max_iter)
+        d.tol = float(tol)
+        if mlp is not None:
+            net, params, mean, std, feat_len = mlp
+            d.mlp_params = params.data_ptr()
+            d.h1, d.h2 = net.desc.h1, net.desc.h2
+            d.feat_len = int(feat_len)
+            d.feat_mean = mean.data_ptr()
+            d.feat_std = std.data_ptr()
+        self.desc = d
+        self.M = d.n_probe * 2 * wfs.n_valid
+        n = C.c_size_t(0)
+        _check(lib.synim_misreg_workspace(C.byref(d), C.byref(n)), "misreg_workspace")
+        self.ws = torch.empty(n.value, dtype=torch.uint8, device=probes.device)
+        self._h = C.c_void_p(0)
+        _check(lib.synim_misreg_create(C.byref(d), self.ws.data_ptr(), self.ws.numel(),
+                                       _stream_handle(probes.device), C.byref(self._h)),
+               "misreg_create")
+        self._side = torch.cuda.Stream(device=probes.device)
+
+    def slopes(self, theta, jac=False):
+        """S [B][M] (and J [B][4][M]) at theta (GPU float64 [B][4])."""
+        torch = _torch()
+        B = theta.shape[0]
+        s = torch.empty((B, self.M), dtype=torch.float32, device=theta.device)
+        j = torch.empty((B, 4, self.M), dtype=torch.float32, device=theta.device) if jac else None
+        _check(load().synim_misreg_slopes(self._h, theta.contiguous().data_ptr(), B,
+                                          s.data_ptr(), j.data_ptr() if jac else None,
+                                          _stream_handle(theta.device)), "misreg_slopes")
+        return (s, j) if jac else s
+
+    def features(self, slopes, mean=None, std=None):
+        torch = _torch()
+        B = slopes.shape[0]
+        x = torch.empty((B, self.M), dtype=torch.float32, device=slopes.device)
+        _check(load().synim_misreg_features(
+            self._h, slopes.data_ptr(), B, mean.data_ptr() if mean is not None else None,
+            std.data_ptr() if std is not None else None, x.data_ptr(),
+            _stream_handle(slopes.device)), "misreg_features")
+        return x
+
+    def infer(self, slopes, mode=MISREG_GN, iter_cap=0, use_graph=True):
+        """(theta [B][4] float64, iterations [B] int32) on the GPU."""
+        torch = _torch()
+        _dev_f32(slopes, "slopes")
+        B = slopes.shape[0]
+        th = torch.empty((B, 4), dtype=torch.float64, device=slopes.device)
+        it = torch.empty(B, dtype=torch.int32, device=slopes.device)
+        if use_graph:
+            cur = torch.cuda.current_stream(slopes.device)
+            self._side.wait_stream(cur)
+            sh = self._side.cuda_stream
+        else:
+            sh = _stream_handle(slopes.device)
+        _check(load().synim_misreg_infer(self._h, slopes.data_ptr(), B, mode, th.data_ptr(),
+                                         it.data_ptr(), int(iter_cap), 1 if use_graph else 0, sh),
+               "misreg_infer")
+        if use_graph:
+            cur.wait_stream(self._side)
+        return th, it
+
+    def status(self) -> int:
+        v = C.c_int(0)
+        _check(load().synim_misreg_status(self._h, C.byref(v), _stream_handle(self.ws.device)),
+               "misreg_status")
+        return int(v.value)
+
+    def close(self):
+        if self._h and self._h.value:
+            load().synim_misreg_destroy(self._h)
+            self._h = C.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -36,6 +36,20 @@ class SynimPair(C.Structure):
     _fields_ = [("wfs", C.c_int32), ("dm", C.c_int32), ("A", SynimAffine), ("im", C.c_void_p)]
 
 
+class SynimMlp(C.Structure):
+    _fields_ = [(n, C.c_int32) for n in ("n_in", "h1", "h2", "n_out", "seg0", "len0", "seg1",
+                                         "len1")]
+
+
+class SynimMisregDesc(C.Structure):
+    _fields_ = [("wfs", SynimWfs), ("probes", C.c_void_p), ("n_probe", C.c_int32),
+                ("H_in", C.c_int32), ("W_in", C.c_int32), ("kappa", C.c_double),
+                ("max_batch", C.c_int32), ("theta_lo", C.c_double * 4),
+                ("theta_hi", C.c_double * 4), ("max_iter", C.c_int32), ("tol", C.c_double),
+                ("mlp_params", C.c_void_p), ("h1", C.c_int32), ("h2", C.c_int32),
+                ("feat_len", C.c_int32), ("feat_mean", C.c_void_p), ("feat_std", C.c_void_p)]
+
+
 P = C.c_void_p
 I = C.c_int
 SZ = C.c_size_t
@@ -76,6 +90,18 @@ SIGNATURES = {
     "synim_batch_autotune": (I, [P, I, C.POINTER(C.c_float), C.POINTER(I), P]),
     "synim_batch_config": (I, [P, C.POINTER(I)]),
     "synim_batch_destroy": (None, [P]),
+    "synim_mlp_param_count": (SZ, [C.POINTER(SynimMlp)]),
+    "synim_mlp_scratch_floats": (SZ, [C.POINTER(SynimMlp), I]),
+    "synim_mlp_forward": (I, [C.POINTER(SynimMlp), P, P, I, P, P, P]),
+    "synim_mlp_backward": (I, [C.POINTER(SynimMlp), P, P, I, P, P, P, P, P, P]),
+    "synim_adam_step": (I, [P, P, P, P, SZ, I, C.c_float, C.c_float, C.c_float, C.c_float, P]),
+    "synim_misreg_workspace": (I, [C.POINTER(SynimMisregDesc), C.POINTER(SZ)]),
+    "synim_misreg_create": (I, [C.POINTER(SynimMisregDesc), P, SZ, P, C.POINTER(P)]),
+    "synim_misreg_slopes": (I, [P, P, I, P, P, P]),
+    "synim_misreg_features": (I, [P, P, I, P, P, P, P]),
+    "synim_misreg_infer": (I, [P, P, I, I, P, P, I, I, P]),
+    "synim_misreg_status": (I, [P, C.POINTER(I), P]),
+    "synim_misreg_destroy": (None, [P]),
     "synim_im_candidates": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(I), I,
                                 C.POINTER(I)]),
 }

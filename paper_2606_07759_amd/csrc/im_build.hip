@@ -1284,16 +1284,20 @@ struct synim_batch {
   std::vector<synim_wfs> wfs;
   std::vector<synim_dm> dms;
   std::vector<synim_pair> pairs;
-  std::vector<int> order;        // pair indices sorted by DM
+  std::vector<int> group;        // pairs of one group share an IF stack (and its reads)
+  int n_groups = 0;
+  int planes = 1;                // 1: IM; 5: IM + 4 Jacobian planes (dmaps required)
+  std::vector<int> order;        // pair indices sorted by group
   const Variant* var = nullptr;
   std::vector<Plan> plans;       // per pair (original index)
   char* ws = nullptr;
   size_t ws_bytes = 0;
   size_t off_maps = 0, off_pairs = 0, off_recs = 0, off_groups = 0, off_ctr = 0, off_scratch = 0;
-  size_t off_jobs = 0;
+  size_t off_jobs = 0, off_dmaps = 0;
   int max_nv = 0, max_e = 0, max_slots = 0, max_tiles = 0;
   int n_recs = 0;
   int rec_off[8] = {}, rec_cnt[8] = {}, xcd_items[8] = {};
+  std::vector<SuperChunk> recs_host;   // to count the items of the first groups
   int G = 0;
   bool vec4 = true;
   MapD* staging = nullptr;       // pinned host copy of the maps
@@ -1316,14 +1320,20 @@ int batch_layout(synim_batch* b, const Variant& v, size_t* bytes) {
     return at;
   };
   b->off_maps = take(np * sizeof(MapD));
+  b->off_dmaps = take(b->planes > 1 ? np * sizeof(Map4) : 0);
   b->off_jobs = take(np * sizeof(PlanJob));
   b->off_pairs = take(np * sizeof(PairDesc));
-  b->off_groups = take(b->dms.size() * sizeof(int2));
-  b->off_ctr = take(8 * sizeof(int));
+  b->off_groups = take(b->n_groups * sizeof(int2));
+  b->off_ctr = take(8 * MAX_PLANES * sizeof(int));   // one set of 8 per plane (grid z)
   b->off_scratch = take(64 * sizeof(float));
   // upper bound on the records: every DM chunk of length 1
   long max_recs = 0;
-  for (const auto& d : b->dms) max_recs += d.n_act;
+  for (int gi = 0; gi < b->n_groups; ++gi)
+    for (int i = 0; i < np; ++i)
+      if (b->group[i] == gi) {
+        max_recs += b->dms[b->pairs[i].dm].n_act;
+        break;
+      }
   b->off_recs = take(max_recs * sizeof(SuperChunk));
   b->plans.assign(np, Plan{});
   for (int i = 0; i < np; ++i) {
@@ -1334,7 +1344,7 @@ int batch_layout(synim_batch* b, const Variant& v, size_t* bytes) {
     if (tiles_for_variant(w, pr.A, v, cand, cost, 64) == 0) return SYNIM_E_UNSUPPORTED;
     Plan& P = b->plans[i];
     P.d = cand[0];
-    P.L = layout(w, P.d, 1);
+    P.L = layout(w, P.d, b->planes);
     const size_t at = take(P.L.total);
     P.ws = reinterpret_cast<char*>(at);   // offset until the workspace is bound
   }
@@ -1399,28 +1409,30 @@ int batch_bind(synim_batch* b, const Variant& v, hipStream_t st) {
   const int chunk = chunk_for(act_tiles, b->G);
   // pair table in DM order, groups, super-chunk records
   std::vector<PairDesc> pd(np);
-  std::vector<int2> groups(b->dms.size(), make_int2(0, 0));
+  std::vector<int2> groups(b->n_groups, make_int2(0, 0));
+  std::vector<int> group_nact(b->n_groups, 0);
   int at = 0;
-  for (int d = 0; d < (int)b->dms.size(); ++d) {
-    groups[d] = make_int2(at, 0);
+  for (int gi = 0; gi < b->n_groups; ++gi) {
+    groups[gi] = make_int2(at, 0);
     for (int i : b->order)
-      if (b->pairs[i].dm == d) {
-        const synim_dm& dm = b->dms[d];
+      if (b->group[i] == gi) {
+        const synim_dm& dm = b->dms[b->pairs[i].dm];
         pd[at++] = pair_desc(b->plans[i], dm.ifs, dm.n_act, dm.H_in, dm.W_in,
                              b->wfs[b->pairs[i].wfs].n_valid, b->pairs[i].im, chunk);
-        groups[d].y++;
+        groups[gi].y++;
+        group_nact[gi] = dm.n_act;
       }
   }
   std::vector<std::vector<SuperChunk>> per(8);
   long sc = 0;
-  for (int d = 0; d < (int)b->dms.size(); ++d) {
-    if (groups[d].y == 0) continue;
+  for (int gi = 0; gi < b->n_groups; ++gi) {
+    if (groups[gi].y == 0) continue;
     int items = 0;
-    for (int k = 0; k < groups[d].y; ++k) items += pd[groups[d].x + k].n_tiles;
-    const int nch = (b->dms[d].n_act + chunk - 1) / chunk;
+    for (int k = 0; k < groups[gi].y; ++k) items += pd[groups[gi].x + k].n_tiles;
+    const int nch = (group_nact[gi] + chunk - 1) / chunk;
     for (int c = 0; c < nch; ++c, ++sc) {
       const int x = (int)(sc % 8);
-      per[x].push_back(SuperChunk{0, d, c, items});
+      per[x].push_back(SuperChunk{0, gi, c, items});
     }
   }
   std::vector<SuperChunk> recs;
@@ -1436,12 +1448,15 @@ int batch_bind(synim_batch* b, const Variant& v, hipStream_t st) {
     b->xcd_items[x] = acc;
   }
   b->n_recs = (int)recs.size();
+  b->recs_host = recs;
   std::vector<PlanJob> jobs(np);
   const MapD* maps_dev = reinterpret_cast<const MapD*>(b->ws + b->off_maps);
   b->max_nv = b->max_e = b->max_slots = b->max_tiles = 0;
   for (int i = 0; i < np; ++i) {
     const synim_pair& pr = b->pairs[i];
-    jobs[i] = make_job(b->wfs[pr.wfs], to_map(pr.A), maps_dev + i, Map4{}, nullptr, 1,
+    const Map4* dmaps_dev =
+        b->planes > 1 ? reinterpret_cast<const Map4*>(b->ws + b->off_dmaps) + i : nullptr;
+    jobs[i] = make_job(b->wfs[pr.wfs], to_map(pr.A), maps_dev + i, Map4{}, dmaps_dev, b->planes,
                        b->plans[i]);
     b->max_nv = std::max(b->max_nv, jobs[i].nv);
     b->max_e = std::max(b->max_e, jobs[i].PH * jobs[i].PW);
@@ -1461,8 +1476,27 @@ int batch_bind(synim_batch* b, const Variant& v, hipStream_t st) {
   return SYNIM_OK;
 }
 
-int batch_enqueue(synim_batch* b, hipStream_t st) {
-  const int np = (int)b->pairs.size();
+// Enqueue plans and the stream launch for the pairs of the first n_groups
+// groups (all by default): their records form a prefix of every XCD queue,
+// since the records are dealt group-major; plan jobs follow the group order
+// only when each pair is its own group (the misregistration batches).
+int batch_enqueue(synim_batch* b, hipStream_t st, int n_groups = -1) {
+  int np = (int)b->pairs.size();
+  int items[8];
+  for (int x = 0; x < 8; ++x) items[x] = b->xcd_items[x];
+  if (n_groups >= 0 && n_groups < b->n_groups) {
+    np = 0;
+    for (int i = 0; i < (int)b->pairs.size(); ++i) np += b->group[i] < n_groups ? 1 : 0;
+    for (int x = 0; x < 8; ++x) {
+      int acc = 0;
+      for (int r = 0; r < b->rec_cnt[x]; ++r) {
+        const SuperChunk& rc = b->recs_host[b->rec_off[x] + r];
+        if (rc.dm >= n_groups) break;
+        acc += rc.items;
+      }
+      items[x] = acc;
+    }
+  }
   int rc = enqueue_plans(PlanJob{}, reinterpret_cast<const PlanJob*>(b->ws + b->off_jobs), np,
                          b->max_nv, b->max_e, b->max_slots, b->max_tiles, st);
   if (rc != SYNIM_OK) return rc;
@@ -1473,14 +1507,14 @@ int batch_enqueue(synim_batch* b, hipStream_t st) {
   for (int x = 0; x < 8; ++x) {
     g.rec_off[x] = b->rec_off[x];
     g.rec_cnt[x] = b->rec_cnt[x];
-    g.xcd_items[x] = b->xcd_items[x];
+    g.xcd_items[x] = items[x];
   }
   g.counters = reinterpret_cast<int*>(b->ws + b->off_ctr);
   g.scratch = reinterpret_cast<float*>(b->ws + b->off_scratch);
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, g.counters, 8);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, g.counters, 8 * b->planes);
   SYNIM_HIP_TRY(hipGetLastError());
   StreamFn fn = pick_fn(*b->var, b->vec4, false);
-  hipLaunchKernelGGL(fn, dim3((unsigned)b->G, 1, 1), dim3(b->var->BLOCK), 0, st, g);
+  hipLaunchKernelGGL(fn, dim3((unsigned)b->G, 1, b->planes), dim3(b->var->BLOCK), 0, st, g);
   SYNIM_HIP_TRY(hipGetLastError());
   return SYNIM_OK;
 }
@@ -1513,15 +1547,21 @@ int batch_check(const synim_wfs* wfs, int n_wfs, const synim_dm* dms, int n_dm,
   return SYNIM_OK;
 }
 
+// group: nullptr groups the pairs by DM (pairs sharing a DM share its reads).
 void batch_fill(synim_batch* b, const synim_wfs* wfs, int n_wfs, const synim_dm* dms, int n_dm,
-                const synim_pair* pairs, int n_pairs) {
+                const synim_pair* pairs, int n_pairs, const int* group = nullptr,
+                int n_groups = 0, int planes = 1) {
   b->wfs.assign(wfs, wfs + n_wfs);
   b->dms.assign(dms, dms + n_dm);
   b->pairs.assign(pairs, pairs + n_pairs);
+  b->planes = planes;
+  b->group.resize(n_pairs);
+  for (int i = 0; i < n_pairs; ++i) b->group[i] = group ? group[i] : pairs[i].dm;
+  b->n_groups = group ? n_groups : n_dm;
   b->order.resize(n_pairs);
   for (int i = 0; i < n_pairs; ++i) b->order[i] = i;
   std::stable_sort(b->order.begin(), b->order.end(),
-                   [&](int x, int y) { return pairs[x].dm < pairs[y].dm; });
+                   [&](int x, int y) { return b->group[x] < b->group[y]; });
 }
 
 }  // namespace
@@ -1702,3 +1742,5 @@ extern "C" void synim_batch_destroy(synim_batch* b) {
   if (b->staging) (void)hipHostFree(b->staging);
   delete b;
 }
+
+#include "misreg.inc"

@@ -1,0 +1,202 @@
+"""Learned misregistration estimator: data synthesis, training and evaluation.
+
+Everything that computes runs in the library's HIP kernels: probe slopes come
+from the batched build (``Misreg.slopes``), the features from
+``Misreg.features``, and the MLP is trained by the hand-written forward,
+backward and Adam kernels.  torch provides device memory; numpy draws the
+seeded labels and noise.
+
+Readings of the learned-fit workload (the training recipe is not in the paper):
+* probes: Noll Zernikes 2-21 fitted by the 9x9 DM, on the 8x8 SCAO WFS;
+* labels: shift U(-1, 1) subaperture per axis, rotation U(-1, 1) deg,
+  magnification U(0.98, 1.02), scaled to [-1, 1] for the network;
+* noise: per-sample SNR U(20, 200), sigma = RMS(S(theta)) / SNR, i.i.d.
+  Gaussian on every slope;
+* inputs: 2 x feat_len (x and y slopes, probe-major, zero-padded), each
+  feature standardised with the training-set mean and std;
+* training: He-normal init (seeded), Adam (1e-3, 0.9, 0.999, 1e-8), batch 256,
+  a 90/10 train/validation split, early stop on validation MSE.
+"""
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+import workloads as wl
+
+from . import MISREG_GN, MISREG_MLP, MISREG_MLP_GN, Misreg, Mlp, Wfs, adam_step
+
+
+@dataclass
+class ProbeSystem:
+    wfs: Wfs
+    probes: "object"        # torch [n_probe][128][128]
+    lo: np.ndarray
+    hi: np.ndarray
+    n_probe: int
+    n_valid: int
+
+    @property
+    def M(self) -> int:
+        return self.n_probe * 2 * self.n_valid
+
+
+def probe_system(device="cuda") -> ProbeSystem:
+    import torch
+    pc = wl.probe_config()
+    cfg = pc.scao
+    wfs = Wfs.from_numpy(cfg.pupil, cfg.p, cfg.valid, device=device)
+    probes = torch.from_numpy(pc.probe_maps).to(device)
+    return ProbeSystem(wfs, probes, wl.LABEL_LO.copy(), wl.LABEL_HI.copy(), len(pc.modes),
+                       cfg.n_valid)
+
+
+def draw(seeds, M: int):
+    """Labels theta [n][4], SNRs [n] and unit-normal noise [n][M] per seed."""
+    th = np.empty((len(seeds), 4))
+    snr = np.empty(len(seeds))
+    noise = np.empty((len(seeds), M), dtype=np.float32)
+    for i, s in enumerate(seeds):
+        t, r, rng = wl.draw_misreg_labels(int(s))
+        th[i] = t
+        snr[i] = r
+        noise[i] = rng.standard_normal(M)
+    return th, snr, noise
+
+
+def synthesize(ctx: Misreg, theta, snr, noise, batch: int):
+    """Noisy probe slopes [n][M] (GPU float32) for the given labels."""
+    import torch
+    dev = ctx.probes.device
+    n = theta.shape[0]
+    out = torch.empty((n, ctx.M), dtype=torch.float32, device=dev)
+    th = torch.from_numpy(theta).to(dev)
+    nz = torch.from_numpy(noise).to(dev)
+    sn = torch.from_numpy(snr).to(dev).float()
+    for a in range(0, n, batch):
+        b = min(n, a + batch)
+        s = ctx.slopes(th[a:b].contiguous())
+        rms = torch.sqrt((s * s).mean(dim=1, keepdim=True))
+        out[a:b] = s + nz[a:b] * (rms / sn[a:b, None])
+    return out
+
+
+def net_for(system: ProbeSystem, feat_len: int = 4000, h1: int = 512, h2: int = 256) -> Mlp:
+    nN = system.n_probe * system.n_valid
+    return Mlp(2 * feat_len, h1, h2, 4, ((0, nN), (feat_len, nN)))
+
+
+def he_init(net: Mlp, seed: int):
+    """He-normal weights, zero biases, packed (float32, host)."""
+    rng = wl.rng_for(seed)
+    d = net.desc
+    shapes = [(d.h1, d.n_in), (d.h1,), (d.h2, d.h1), (d.h2,), (d.n_out, d.h2), (d.n_out,)]
+    parts = []
+    for sh in shapes:
+        if len(sh) == 2:
+            parts.append(rng.standard_normal(sh).ravel() * math.sqrt(2.0 / sh[1]))
+        else:
+            parts.append(np.zeros(sh))
+    return np.concatenate(parts).astype(np.float32)
+
+
+@dataclass
+class Trained:
+    net: Mlp
+    params: "object"
+    mean: "object"
+    std: "object"
+    feat_len: int
+    history: list
+    seconds: float
+
+
+def train(system: ProbeSystem, slopes, theta, *, feat_len=4000, epochs=40, batch=256, lr=1e-3,
+          seed=0, val_frac=0.1, patience=6, log=None) -> Trained:
+    """Train the estimator on (noisy slopes [n][M] GPU, theta [n][4] numpy)."""
+    import torch
+    dev = slopes.device
+    net = net_for(system, feat_len)
+    ctx = Misreg(system.wfs, system.probes, system.lo, system.hi, max_batch=1)
+    raw = ctx.features(slopes)                      # compact features, unstandardised
+    n = raw.shape[0]
+    n_val = max(1, int(round(val_frac * n)))
+    n_tr = n - n_val
+    mean = raw[:n_tr].mean(dim=0)
+    std = raw[:n_tr].std(dim=0).clamp_min(1e-12)
+    x = ctx.features(slopes, mean.contiguous(), std.contiguous())
+    ctx.close()
+    lo = torch.from_numpy(system.lo).to(dev)
+    hi = torch.from_numpy(system.hi).to(dev)
+    y = ((torch.from_numpy(theta).to(dev) - lo) / (hi - lo) * 2 - 1).float().contiguous()
+    params = torch.from_numpy(he_init(net, seed)).to(dev)
+    grads = torch.zeros_like(params)
+    m = torch.zeros_like(params)
+    v = torch.zeros_like(params)
+    scratch = net.scratch(batch, device=dev)
+    vscratch = net.scratch(n_val, device=dev)
+    out = torch.empty((batch, 4), dtype=torch.float32, device=dev)
+    loss = torch.zeros(1, dtype=torch.float32, device=dev)
+    g = torch.Generator(device="cpu").manual_seed(seed)
+    best, best_params, bad, step, hist = float("inf"), params.clone(), 0, 0, []
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = torch.randperm(n_tr, generator=g).to(dev)
+        tot = 0.0
+        nb = n_tr // batch
+        for k in range(nb):
+            idx = perm[k * batch:(k + 1) * batch]
+            xb = x[idx].contiguous()
+            yb = y[idx].contiguous()
+            net.forward(params, xb, scratch, out)
+            net.backward(params, xb, scratch, out, yb, grads, loss)
+            step += 1
+            adam_step(params, grads, m, v, step, lr=lr)
+            tot += float(loss.item()) if k == nb - 1 else 0.0
+        yv = net.forward(params, x[n_tr:].contiguous(), vscratch)
+        vl = float(((yv - y[n_tr:]) ** 2).mean().item())
+        hist.append((ep, tot, vl))
+        if log:
+            log(f"epoch {ep}: train(last batch) {tot:.5f} val {vl:.5f}")
+        if vl < best:
+            best, best_params, bad = vl, params.clone(), 0
+        else:
+            bad += 1
+            if bad >= patience:
+                break
+    torch.cuda.synchronize()
+    return Trained(net, best_params, mean.contiguous(), std.contiguous(), feat_len, hist,
+                   time.perf_counter() - t0)
+
+
+def estimator(system: ProbeSystem, trained: Optional[Trained], max_batch: int,
+              max_iter: int = 20) -> Misreg:
+    mlp = None
+    if trained is not None:
+        mlp = (trained.net, trained.params, trained.mean, trained.std, trained.feat_len)
+    return Misreg(system.wfs, system.probes, system.lo, system.hi, max_batch=max_batch,
+                  max_iter=max_iter, mlp=mlp)
+
+
+def time_fit(ctx: Misreg, slopes, mode, reps=20, iter_cap=0):
+    """Median and p95 wall time (ms) of one fit call on the GPU (graph replay)."""
+    import torch
+    ctx.infer(slopes, mode, iter_cap=iter_cap)            # capture
+    torch.cuda.synchronize()
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        ctx.infer(slopes, mode, iter_cap=iter_cap)
+        torch.cuda.synchronize()
+        ts.append((time.perf_counter() - t) * 1e3)
+    ts = np.sort(np.array(ts))
+    return float(np.median(ts)), float(ts[int(0.95 * (len(ts) - 1))])
+
+
+__all__ = ["ProbeSystem", "probe_system", "draw", "synthesize", "net_for", "he_init", "train",
+           "estimator", "time_fit", "MISREG_GN", "MISREG_MLP", "MISREG_MLP_GN"]
