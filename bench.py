@@ -38,18 +38,18 @@ def log(*a):
 
 
 # ------------------------------------------------------------ algorithmic bytes
-def touched_if_pixels(cfg, A) -> int:
-    """|S|: IF pixels with a non-zero bilinear weight for some sample that the
-    central differences read (the 4-neighbours of every pupil pixel of a valid
-    subaperture).  Depends on the geometry only, not on any kernel."""
+def touched_mask(pupil, p: int, valid, A, grid_n: int):
+    """Boolean [grid_n][grid_n] mask of the IF pixels with a non-zero bilinear
+    weight for some sample that the central differences read (the
+    4-neighbours of every pupil pixel of a valid subaperture).  Depends on the
+    geometry only, not on any kernel."""
     import numpy as np
-    H, W = cfg.pupil.shape
-    p = cfg.p
+    H, W = pupil.shape
     ns = W // p
     use = np.zeros((H, W), bool)
-    for k in cfg.valid:
+    for k in valid:
         v, u = divmod(int(k), ns)
-        use[v * p:(v + 1) * p, u * p:(u + 1) * p] = cfg.pupil[v * p:(v + 1) * p, u * p:(u + 1) * p] > 0
+        use[v * p:(v + 1) * p, u * p:(u + 1) * p] = pupil[v * p:(v + 1) * p, u * p:(u + 1) * p] > 0
     Q = np.zeros((H + 2, W + 2), bool)          # haloed sample grid
     Q[1:-1, 2:] |= use
     Q[1:-1, :-2] |= use
@@ -64,15 +64,19 @@ def touched_if_pixels(cfg, A) -> int:
     j = np.floor(ys).astype(np.int64)
     a = xs - i
     c = ys - j
-    Hi = Wi = cfg.grid.grid_n
-    S = np.zeros((Hi + 2, Wi + 2), bool)
+    S = np.zeros((grid_n, grid_n), bool)
     for di, dj, w in ((0, 0, (1 - a) * (1 - c)), (1, 0, a * (1 - c)), (0, 1, (1 - a) * c), (1, 1, a * c)):
         nz = w != 0
         ii = i[nz] + di
         jj = j[nz] + dj
-        ok = (ii >= 0) & (ii < Wi) & (jj >= 0) & (jj < Hi)
+        ok = (ii >= 0) & (ii < grid_n) & (jj >= 0) & (jj < grid_n)
         S[jj[ok], ii[ok]] = True
-    return int(S.sum())
+    return S
+
+
+def touched_if_pixels(cfg, A) -> int:
+    """|S| of one SCAO workload (see touched_mask)."""
+    return int(touched_mask(cfg.pupil, cfg.p, cfg.valid, A, cfg.grid.grid_n).sum())
 
 
 # ----------------------------------------------------------------- CPU baseline
@@ -135,6 +139,93 @@ def stored_traffic(n_launch_bytes):
         return None
 
 
+# ------------------------------------------------------------- further legs
+def _event_ms(fn, reps: int):
+    """Mean ms of fn() over reps, HIP events on torch's current stream (every
+    launch of fn is ordered on it)."""
+    import torch
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    fn()
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def mcao_leg(synim, dev, reps: int = 10):
+    """Multi-WFS batch: 6 LGS WFS x 3 DMs (18 pair maps) in one persistent
+    launch, replayed as a hipGraph.  Algorithmic bytes: each DM's IF pixels
+    touched by the union of its 6 WFS footprints, read once, plus every
+    pair's IM."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    cfg = wl.mcao(0)
+    stacks = [wl.if_stack_torch(g, dev) for g in cfg.grids]
+    wfs = [synim.Wfs.from_numpy(P, cfg.p, v, device=dev) for P, v in zip(cfg.pupils, cfg.valids)]
+    n_out = cfg.n_sub * cfg.p
+    maps = [synim.affine_from_geometry(pr.geometry, 512, 512, n_out, n_out) for pr in cfg.pairs]
+    B = synim.Batch(wfs, stacks, [(pr.wfs, pr.dm, A) for pr, A in zip(cfg.pairs, maps)], device=dev)
+    tuned = B.autotune(6)
+    cfg_b = B.config()
+    ms = _event_ms(B.run_graph, reps)
+    if B.status() != 0:
+        raise RuntimeError("MCAO batch plan status non-zero")
+    byts = 0
+    cols = 0
+    for d, g in enumerate(cfg.grids):
+        U = np.zeros((512, 512), bool)
+        for pr, A in zip(cfg.pairs, maps):
+            if pr.dm == d:
+                U |= touched_mask(cfg.pupils[pr.wfs], cfg.p, cfg.valids[pr.wfs], A, 512)
+                byts += 8 * len(cfg.valids[pr.wfs]) * g.n_act
+                cols += g.n_act
+        byts += 4 * int(U.sum()) * g.n_act
+    B.close()
+    del stacks
+    torch.cuda.empty_cache()
+    return {"workload": "MCAO 6 LGS WFS x 3 DMs (81^2/47^2/37^2 on 512^2), 68x68 subap x 7 px, "
+                        "18 pair maps, one persistent launch (hipGraph replay)",
+            "ms_per_batch": ms, "im_columns": cols, "columns_per_s": cols / (ms * 1e-3),
+            "algorithmic_bytes": byts, "achieved_GBs": byts / (ms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": byts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "config": cfg_b, "autotune_ms": tuned}
+
+
+def jacobian_leg(synim, dev, reps: int = 50):
+    """Adjoint workload: 8x8 SCAO, 81 IFs; IM + 4 Jacobian planes, and the VJP."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    cfg = wl.scao_small()
+    F = torch.from_numpy(wl.if_stack(cfg.grid)).to(dev)
+    A, dA = synim.affine_from_misreg(cfg.theta, 96, 96, 80, 80)
+    wfs = synim.Wfs.from_numpy(cfg.pupil, cfg.p, cfg.valid, device=dev)
+    ws = torch.empty(synim.im_workspace_bytes(wfs, A, 5), dtype=torch.uint8, device=dev)
+    g = torch.from_numpy(np.random.default_rng(0).standard_normal((81, 2 * cfg.n_valid))
+                         .astype(np.float32)).to(dev)
+    jac = _event_ms(lambda: synim.im_jacobian(F, A, dA, wfs, with_im=True, ws=ws), reps)
+    vjp = _event_ms(lambda: synim.im_vjp(F, A, dA, wfs, g, ws=ws), reps)
+    im = _event_ms(lambda: synim.im_build(F, A, wfs, ws=ws), reps)
+    return {"workload": "8x8 SCAO (81 IFs on 96^2): plan + stream, per call",
+            "im_us": im * 1e3, "im_plus_jacobian_us": jac * 1e3, "vjp_us": vjp * 1e3}
+
+
+def misreg_leg(n_train: int, n_eval: int, epochs: int):
+    """Learned misregistration estimate vs Gauss-Newton (training set, network
+    training and evaluation all on the GPU kernels)."""
+    from paper_2606_07759_amd import learned
+    rep = learned.run(n_train=n_train, n_eval=n_eval, epochs=epochs,
+                      log=lambda m: log("misreg:", m))
+    rep["workload"] = ("20 Zernike probes (Noll 2-21) on the 8x8 SCAO WFS, MLP 2x4000->512->256->4, "
+                       f"{n_train} training samples, {n_eval} held-out seeds")
+    return rep
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -143,6 +234,13 @@ def main():
     ap.add_argument("--seed", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tune", type=int, default=32,
+                    help="stream-kernel configurations the autotuner times before the run")
+    ap.add_argument("--no-legs", action="store_true",
+                    help="skip the MCAO, Jacobian and misregistration legs")
+    ap.add_argument("--misreg-train", type=int, default=50_000)
+    ap.add_argument("--misreg-eval", type=int, default=1000)
+    ap.add_argument("--misreg-epochs", type=int, default=60)
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -183,6 +281,10 @@ def main():
     bytes_per_col = 4 * S + 8 * cfg.n_valid
     launch_bytes = bytes_per_col * n_act
 
+    log("autotuning the stream kernel")
+    tune_ms = synim.im_autotune(Fd, A, wfs, max_candidates=args.tune, ws=ws)
+    chosen = synim.im_config(wfs, A)
+    log(f"chosen {chosen} ({min(tune_ms):.3f} ms best of {len(tune_ms)})")
     for _ in range(args.warmup):
         synim.im_plan(wfs, A, ws=ws)
         synim.im_apply(Fd, A, wfs, ws, out=out)
@@ -206,6 +308,16 @@ def main():
     apply_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     achieved = launch_bytes / (apply_ms * 1e-3) / 1e9
     traffic = stored_traffic(launch_bytes)
+    del Fd
+    torch.cuda.empty_cache()
+    legs = {}
+    if not args.no_legs:
+        log("leg: MCAO batch")
+        legs["mcao_batch"] = mcao_leg(synim, dev)
+        log("leg: Jacobian / VJP")
+        legs["adjoint"] = jacobian_leg(synim, dev)
+        log("leg: learned misregistration vs Gauss-Newton")
+        legs["misreg_fit"] = misreg_leg(args.misreg_train, args.misreg_eval, args.misreg_epochs)
     rec = {
         "metric": METRIC,
         "value": n_act / (ms_step * 1e-3),
@@ -222,13 +334,14 @@ def main():
         "config": {"workload": f"ELT SCAO IM: 80x80 subap x 6 px, 480-px pupil 28% obscured, "
                                f"{n_act} Gaussian IFs on 512^2, seed {args.seed}",
                    "n_act": n_act, "n_valid": cfg.n_valid, "if_grid": 512,
-                   "theta": [float(v) for v in cfg.theta]},
+                   "theta": [float(v) for v in cfg.theta], "kernel_config": chosen},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": achieved / PEAK_HBM_GBS, "traffic": traffic},
         "cpu_baseline": cpu,
         "detail": {"stream_kernel_ms": apply_ms, "plan_plus_stream_ms": ms_step,
                    "algorithmic_bytes_per_column": bytes_per_col,
                    "touched_if_pixels_per_column": S, "algorithmic_bytes_per_launch": launch_bytes},
+        "legs": legs,
     }
     print(json.dumps(rec), flush=True)
 

@@ -214,16 +214,25 @@ int synim_im_autotune(const float* ifs, int n_act, int H_in, int W_in, const syn
                       const synim_wfs* wfs, float* im, void* ws, size_t ws_bytes,
                       int max_candidates, float* times_ms, int* n_tried, void* stream);
 
-/* The configuration plan/apply would use now: out7 (host) = block size,
+/* The configuration plan/apply would use now: out8 (host) = block size,
  * lanes per subaperture, patch rows, patch columns, tile width and height in
- * subapertures, pipeline stages. */
-int synim_im_config(const synim_wfs* wfs, const synim_affine* A, int* out7);
+ * subapertures, pipeline stages, schedule: 0 = short actuator chunks dealt
+ * round-robin to the XCDs; 1 = one chunk per XCD with every tile of it
+ * running at once, one tile per workgroup; E >= 2 = as 1, with the tiles of
+ * an XCD kept within one block of E actuators of each other. */
+int synim_im_config(const synim_wfs* wfs, const synim_affine* A, int* out8);
 
 /* The candidate configurations synim_im_autotune tries, in its order (cost
- * model first): out7 (host, [max_out][7]) as synim_im_config; *n_out (host)
+ * model first): out8 (host, [max_out][8]) as synim_im_config; *n_out (host)
  * receives the count written. */
-int synim_im_candidates(const synim_wfs* wfs, const synim_affine* A, int* out7, int max_out,
+int synim_im_candidates(const synim_wfs* wfs, const synim_affine* A, int* out8, int max_out,
                         int* n_out);
+
+/* Pin the configuration later plan/apply/build calls use for this geometry
+ * (as if the autotuner had picked it): config8 (host) as synim_im_config,
+ * one of synim_im_candidates.  Errors: SYNIM_E_NULL, SYNIM_E_SHAPE,
+ * SYNIM_E_UNSUPPORTED (not a candidate for this geometry). */
+int synim_im_set_config(const synim_wfs* wfs, const synim_affine* A, const int* config8);
 
 /* Forget every autotuned configuration. */
 void synim_autotune_clear(void);

@@ -290,29 +290,39 @@ def im_autotune(ifs, A, wfs: Wfs, max_candidates: int = 8, ws=None):
     return [float(times[i]) for i in range(tried.value)]
 
 
-_CFG_KEYS = ("block", "lanes_per_subap", "patch_rows", "patch_cols", "tile_x", "tile_y", "stages")
+_CFG_KEYS = ("block", "lanes_per_subap", "patch_rows", "patch_cols", "tile_x", "tile_y", "stages",
+             "schedule")
 
 
 def im_config(wfs: Wfs, A) -> dict:
     """Kernel configuration plan/apply would use for this geometry now."""
     lib = load()
-    o = (C.c_int * 7)()
+    o = (C.c_int * 8)()
     s = wfs.struct()
     a = _affine_struct(A)
     _check(lib.synim_im_config(C.byref(s), C.byref(a), o), "im_config")
-    return dict(zip(_CFG_KEYS, o[:7]))
+    return dict(zip(_CFG_KEYS, o[:8]))
 
 
-def im_candidates(wfs: Wfs, A, max_out: int = 48) -> list:
+def im_candidates(wfs: Wfs, A, max_out: int = 96) -> list:
     """Candidate kernel configurations in the autotuner's order."""
     lib = load()
-    o = (C.c_int * (7 * max_out))()
+    o = (C.c_int * (8 * max_out))()
     n = C.c_int(0)
     s = wfs.struct()
     a = _affine_struct(A)
     _check(lib.synim_im_candidates(C.byref(s), C.byref(a), o, max_out, C.byref(n)),
            "im_candidates")
-    return [dict(zip(_CFG_KEYS, o[7 * i:7 * i + 7])) for i in range(n.value)]
+    return [dict(zip(_CFG_KEYS, o[8 * i:8 * i + 8])) for i in range(n.value)]
+
+
+def im_set_config(wfs: Wfs, A, config: dict):
+    """Pin one of :func:`im_candidates` for this geometry."""
+    lib = load()
+    o = (C.c_int * 8)(*[int(config[k]) for k in _CFG_KEYS])
+    s = wfs.struct()
+    a = _affine_struct(A)
+    _check(lib.synim_im_set_config(C.byref(s), C.byref(a), o), "im_set_config")
 
 
 def autotune_clear():

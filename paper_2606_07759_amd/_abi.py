@@ -104,6 +104,7 @@ SIGNATURES = {
     "synim_misreg_destroy": (None, [P]),
     "synim_im_candidates": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(I), I,
                                 C.POINTER(I)]),
+    "synim_im_set_config": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(I)]),
 }
 
 

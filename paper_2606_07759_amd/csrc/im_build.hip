@@ -294,6 +294,7 @@ __global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
       J.tile_info[t] = make_int4(0, 0, 0, 0);
     } else {
       J.tile_info[t] = make_int4(y0, bh, off, 0);
+      atomicAdd(J.status + 1, 1);   // non-empty tiles
     }
   }
 }
@@ -357,6 +358,13 @@ struct StreamArgs {
   int out_plane0;            // weight plane that lands in out[0]
   const float* grad;         // VJP: [n_act][2nv]
   double* partials;          // VJP: [4][gridDim.x]
+  // Bounded-lag sync of the workgroups of one XCD (single pair, one chunk
+  // per XCD): every sync_every actuators a workgroup waits until each tile of
+  // its XCD has started the previous block, so the tiles of a chunk read the
+  // rows they share within a few actuators of each other.  0 = off.
+  int sync_every;
+  int* sync_ctr;             // [gridDim.z][8] block entries, zeroed before the launch
+  const int* n_active;       // non-empty tiles (written by the plan)
 };
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -410,6 +418,17 @@ __device__ __forceinline__ void wait_vm(int n) {
     default: __builtin_amdgcn_s_waitcnt(waitcnt_vm(0)); break;
   }
 }
+
+// Coherent read of a counter that other workgroups update with device-scope
+// atomics: a scalar load that misses the scalar cache (glc), waited on the
+// LGKM counter so that the vector-memory pipeline of the wave is untouched.
+__device__ __forceinline__ int load_counter(const int* p) {
+  int v;
+  asm volatile("s_load_dword %0, %1, 0x0 glc\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
+  return v;
+}
+
+constexpr int SYNC_SPIN_MAX = 4000;   // polls before a workgroup stops syncing
 
 // Persistent streaming kernel.  Work items are (actuator chunk, tile) pairs;
 // workgroup b serves the queue of its XCD (b mod 8 - consecutive workgroups are
@@ -528,6 +547,12 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
     }
     const int a0 = chunk_id * P.chunk;
     const int a1 = min(P.n_act, a0 + P.chunk);
+    // XCD sync (single pair only; E >= NST - 1 is guaranteed by the host)
+    const bool sync_on = g.pairs == nullptr && g.sync_every > 0;
+    const int sync_e = sync_on ? g.sync_every : 1;
+    int* sync_ctr = g.sync_ctr + 8 * blockIdx.z + xcd;
+    const int n_part = sync_on ? *g.n_active : 0;
+    bool sync_live = true;
 
     auto consume = [&](const float4* buf, int a) {
       const float* fb = reinterpret_cast<const float*>(buf);
@@ -569,15 +594,48 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
     // The wait counts every vector-memory operation issued after this stage's
     // DMA: the later stages' DMA (NJ each) and, in the IM kernel, the one store
     // of each step since then.
+    //
+    // With the XCD sync on, actuator a0 + j with j a multiple of E opens
+    // block j/E: wave 0 first waits (bounded) until the XCD's block-entry
+    // counter shows that every tile entered block j/E - 1, then lane 0 adds
+    // its own entry right before the block's first DMA.  Those atomics are
+    // vector-memory operations of wave 0, so wave 0's wait also counts the
+    // entries issued after this stage's DMA (E >= NST - 1 keeps the prologue
+    // free of entries other than block 0).  A workgroup that waits too long
+    // stops waiting but keeps adding its entries, so the counts stay exact.
     auto step = [&](auto kc, int a) {
       constexpr int K = decltype(kc)::value;
       const int later = min(NST - 2, a1 - 1 - a);
       const int stores = VJP ? 0 : min(a - a0, NST - 1);
-      wait_vm(later * NJ + stores);
+      const int x = a + NST - 1;   // the actuator this step starts loading
+      int extra = 0;
+      if (sync_on) {
+        const int jx = x - a0;
+        if (wave == 0 && sync_live && x < a1 && jx > 0 && jx % sync_e == 0) {
+          const int target = (jx / sync_e) * n_part;
+          int it = 0;
+          while (load_counter(sync_ctr) < target) {
+            if (++it >= SYNC_SPIN_MAX) {
+              sync_live = false;
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+          }
+        }
+        if (wave == 0) {
+          const int j = a - a0;
+          extra = (j + later) / sync_e - j / sync_e;
+        }
+      }
+      wait_vm(later * NJ + stores + extra);
       __builtin_amdgcn_s_barrier();
-      if (a + NST - 1 < a1) issue(stage_buf<(K + NST - 1) % NST, STAGE_F4>(), a + NST - 1);
+      if (x < a1) {
+        if (sync_on && tid == 0 && (x - a0) % sync_e == 0) atomicAdd(sync_ctr, 1);
+        issue(stage_buf<(K + NST - 1) % NST, STAGE_F4>(), x);
+      }
       consume(stage_buf<K, STAGE_F4>(), a);
     };
+    if (sync_on && tid == 0 && a0 < a1) atomicAdd(sync_ctr, 1);   // block 0
     [&]<int... K>(std::integer_sequence<int, K...>) {
       ((a0 + K < a1 && K < NST - 1 ? issue(stage_buf<K, STAGE_F4>(), a0 + K) : void()), ...);
     }(std::make_integer_sequence<int, NST>{});
@@ -620,6 +678,7 @@ __global__ void vjp_finalize_kernel(const double* __restrict__ partials, int G,
 
 using StreamFn = void (*)(StreamArgs);
 
+
 struct Variant {
   int BLOCK, LPS, RPL, PW, NJ4, NST;   // NJ4: 16-byte DMA instructions per wave per stage
   StreamFn im4, vjp4;                  // 16-byte DMA: rows a multiple of 4 floats, aligned stack
@@ -656,11 +715,23 @@ const Variant kVariants[] = {
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
+// Schedules of the persistent stream kernel over (actuator chunk, tile) items.
+//   SCHED_DYNAMIC  short chunks dealt round-robin to the XCD queues, items
+//                  taken in chunk order (load balance across workgroups);
+//   SCHED_XCD      one chunk per XCD (its eighth of the actuators) and at most
+//                  one tile per workgroup of that XCD: every tile of the XCD's
+//                  chunk runs at once, so neighbouring tiles read the IF rows
+//                  they share at about the same time (one L2 fill), and each
+//                  workgroup loads its weight patches once.
+constexpr int SCHED_DYNAMIC = 0, SCHED_XCD = 1;
+
 struct Dims {
   const Variant* var;
   int PH, PW;
   int TX, TY, NSLOT, n_tiles_x, n_tiles;
   int BWmax, BHmax;
+  int sched;
+  int sync_every;   // SCHED_XCD: actuators per sync block (0 = no sync)
 };
 
 struct WsLayout {
@@ -732,8 +803,12 @@ int tiles_for_variant(const synim_wfs& w, const synim_affine& A, const Variant& 
   return n;
 }
 
-// Every (variant, tile shape) that can run this geometry with the smallest
-// weight patch that fits, cheapest first by the cost model.
+int persistent_grid(StreamFn fn, int block);
+
+// Every (variant, tile shape, schedule) that can run this geometry with the
+// smallest weight patch that fits, cheapest first by the cost model.  The
+// one-chunk-per-XCD schedule is offered for tile shapes with no more tiles
+// than an XCD has resident workgroups (known only with a device present).
 int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double* cost_out,
                    int max_out) {
   int pw_need, ph_need;
@@ -743,30 +818,44 @@ int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double*
     if (kVariants[i].PW >= pw_need && kVariants[i].PH() >= ph_need)
       best_area = std::min(best_area, kVariants[i].PW * kVariants[i].PH());
   if (best_area == INT_MAX) return 0;
-  int n = 0;
+  std::vector<std::pair<double, Dims>> all;
   for (int i = 0; i < kNumVariants; ++i) {
     const Variant& v = kVariants[i];
     if (v.PW * v.PH() != best_area) continue;
     Dims tmp[64];
     double tc[64];
     const int m = tiles_for_variant(w, A, v, tmp, tc, 64);
+    const int G = persistent_grid(v.im4, v.BLOCK);
     for (int k = 0; k < m; ++k) {
-      int at = n;
-      while (at > 0 && cost_out[at - 1] > tc[k]) --at;
-      if (at >= max_out) continue;
-      for (int j = std::min(n, max_out - 1); j > at; --j) {
-        out[j] = out[j - 1];
-        cost_out[j] = cost_out[j - 1];
+      all.push_back({tc[k], tmp[k]});
+      if (G >= 8 && tmp[k].n_tiles <= G / 8) {
+        // sync blocks of E actuators: E >= NST - 1 keeps the pipeline
+        // prologue free of block entries
+        const int e_min = std::max(2, v.NST - 1);
+        const int es[3] = {e_min, std::max(8, e_min), 0};
+        const double f[3] = {0.85, 0.87, 0.9};
+        for (int q = 0; q < 3; ++q) {
+          Dims d = tmp[k];
+          d.sched = SCHED_XCD;
+          d.sync_every = es[q];
+          all.push_back({f[q] * tc[k], d});
+        }
       }
-      out[at] = tmp[k];
-      cost_out[at] = tc[k];
-      if (n < max_out) ++n;
     }
+  }
+  std::stable_sort(all.begin(), all.end(),
+                   [](const std::pair<double, Dims>& a, const std::pair<double, Dims>& b) {
+                     return a.first < b.first;
+                   });
+  const int n = std::min((int)all.size(), max_out);
+  for (int i = 0; i < n; ++i) {
+    out[i] = all[i].second;
+    cost_out[i] = all[i].first;
   }
   return n;
 }
 
-constexpr int MAX_CAND = 48;
+constexpr int MAX_CAND = 96;
 
 // Autotune cache: geometry key -> (variant, tile shape) measured fastest.
 struct TuneKey {
@@ -779,7 +868,7 @@ struct TuneKey {
 };
 struct TuneEntry {
   TuneKey key;
-  int variant, TX, TY, NSLOT;
+  int variant, TX, TY, NSLOT, sched, sync_every;
 };
 std::mutex g_tune_mu;
 TuneEntry g_tune[256];
@@ -805,7 +894,8 @@ int choose_dims(const synim_wfs& w, const synim_affine& A, Dims* d) {
     if (g_tune[i].key == key)
       for (int c = 0; c < n; ++c)
         if (cand[c].var == &kVariants[g_tune[i].variant] && cand[c].TX == g_tune[i].TX &&
-            cand[c].TY == g_tune[i].TY && cand[c].NSLOT == g_tune[i].NSLOT) {
+            cand[c].TY == g_tune[i].TY && cand[c].NSLOT == g_tune[i].NSLOT &&
+            cand[c].sched == g_tune[i].sched && cand[c].sync_every == g_tune[i].sync_every) {
           *d = cand[c];
           return SYNIM_OK;
         }
@@ -822,7 +912,7 @@ WsLayout layout(const synim_wfs& w, const Dims& d, int planes) {
   };
   const size_t nv = (size_t)w.n_valid;
   L.status = take(16 * sizeof(int));
-  L.counters = take(8 * MAX_PLANES * sizeof(int));
+  L.counters = take(16 * MAX_PLANES * sizeof(int));   // work items, then sync blocks
   L.scratch = take(64 * sizeof(float));
   L.origin = take(nv * sizeof(int2));
   L.inv2nk = take(nv * sizeof(double));
@@ -1031,8 +1121,8 @@ int launch_stream(const Plan& P, const float* ifs, int n_act, int H_in, int W_in
   if (G < 0) return SYNIM_E_HIP;
   if (grad && G > GMAX_VJP) return SYNIM_E_SHAPE;
   StreamArgs g{};
-  g.one = pair_desc(P, ifs, n_act, H_in, W_in, nv, out,
-                    chunk_for((long)n_act * d.n_tiles, G));
+  const int chunk = d.sched == SCHED_XCD ? (n_act + 7) / 8 : chunk_for((long)n_act * d.n_tiles, G);
+  g.one = pair_desc(P, ifs, n_act, H_in, W_in, nv, out, chunk);
   g.pairs = nullptr;
   g.counters = P.counters();
   g.scratch = P.scratch();
@@ -1040,7 +1130,10 @@ int launch_stream(const Plan& P, const float* ifs, int n_act, int H_in, int W_in
   g.out_plane0 = plane0;
   g.grad = grad;
   g.partials = P.partials();
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, P.counters(), 8 * MAX_PLANES);
+  g.sync_every = d.sched == SCHED_XCD ? d.sync_every : 0;
+  g.sync_ctr = P.counters() + 8 * MAX_PLANES;
+  g.n_active = P.status() + 1;
+  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(128), 0, st, P.counters(), 16 * MAX_PLANES);
   SYNIM_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(fn, dim3((unsigned)G, 1, nplanes), dim3(v.BLOCK), 0, st, g);
   SYNIM_HIP_TRY(hipGetLastError());
@@ -1128,7 +1221,7 @@ extern "C" int synim_im_autotune(const float* ifs, int n_act, int H_in, int W_in
   if (n_tried) *n_tried = n;
   const TuneKey key = tune_key(*wfs, *A);
   TuneEntry e{key, (int)(cand[best].var - kVariants), cand[best].TX, cand[best].TY,
-              cand[best].NSLOT};
+              cand[best].NSLOT, cand[best].sched, cand[best].sync_every};
   std::lock_guard<std::mutex> lk(g_tune_mu);
   for (int i = 0; i < g_tune_n; ++i)
     if (g_tune[i].key == key) {
@@ -1139,33 +1232,34 @@ extern "C" int synim_im_autotune(const float* ifs, int n_act, int H_in, int W_in
   return SYNIM_OK;
 }
 
-extern "C" int synim_im_config(const synim_wfs* wfs, const synim_affine* A, int* out7) {
-  if (!wfs || !A || !out7) return SYNIM_E_NULL;
+extern "C" int synim_im_config(const synim_wfs* wfs, const synim_affine* A, int* out8) {
+  if (!wfs || !A || !out8) return SYNIM_E_NULL;
   int rc = validate_wfs(wfs);
   if (rc != SYNIM_OK) return rc;
   Dims d{};
   rc = choose_dims(*wfs, *A, &d);
   if (rc != SYNIM_OK) return rc;
-  out7[0] = d.var->BLOCK;
-  out7[1] = d.var->LPS;
-  out7[2] = d.PH;
-  out7[3] = d.PW;
-  out7[4] = d.TX;
-  out7[5] = d.TY;
-  out7[6] = d.var->NST;
+  out8[0] = d.var->BLOCK;
+  out8[1] = d.var->LPS;
+  out8[2] = d.PH;
+  out8[3] = d.PW;
+  out8[4] = d.TX;
+  out8[5] = d.TY;
+  out8[6] = d.var->NST;
+  out8[7] = d.sched == SCHED_XCD ? (d.sync_every > 0 ? d.sync_every : 1) : 0;
   return SYNIM_OK;
 }
 
-extern "C" int synim_im_candidates(const synim_wfs* wfs, const synim_affine* A, int* out7,
+extern "C" int synim_im_candidates(const synim_wfs* wfs, const synim_affine* A, int* out8,
                                    int max_out, int* n_out) {
-  if (!wfs || !A || !out7 || !n_out) return SYNIM_E_NULL;
+  if (!wfs || !A || !out8 || !n_out) return SYNIM_E_NULL;
   int rc = validate_wfs(wfs);
   if (rc != SYNIM_OK) return rc;
   Dims cand[MAX_CAND];
   double cost[MAX_CAND];
   const int n = std::min(max_out, candidate_dims(*wfs, *A, cand, cost, MAX_CAND));
   for (int i = 0; i < n; ++i) {
-    int* o = out7 + 7 * i;
+    int* o = out8 + 8 * i;
     o[0] = cand[i].var->BLOCK;
     o[1] = cand[i].var->LPS;
     o[2] = cand[i].PH;
@@ -1173,9 +1267,39 @@ extern "C" int synim_im_candidates(const synim_wfs* wfs, const synim_affine* A, 
     o[4] = cand[i].TX;
     o[5] = cand[i].TY;
     o[6] = cand[i].var->NST;
+    o[7] = cand[i].sched == SCHED_XCD ? (cand[i].sync_every > 0 ? cand[i].sync_every : 1) : 0;
   }
   *n_out = n;
   return SYNIM_OK;
+}
+
+extern "C" int synim_im_set_config(const synim_wfs* wfs, const synim_affine* A,
+                                   const int* config8) {
+  if (!wfs || !A || !config8) return SYNIM_E_NULL;
+  int rc = validate_wfs(wfs);
+  if (rc != SYNIM_OK) return rc;
+  Dims cand[MAX_CAND];
+  double cost[MAX_CAND];
+  const int n = candidate_dims(*wfs, *A, cand, cost, MAX_CAND);
+  for (int c = 0; c < n; ++c) {
+    const Dims& d = cand[c];
+    const int sched = d.sched == SCHED_XCD ? (d.sync_every > 0 ? d.sync_every : 1) : 0;
+    if (d.var->BLOCK != config8[0] || d.var->LPS != config8[1] || d.PH != config8[2] ||
+        d.PW != config8[3] || d.TX != config8[4] || d.TY != config8[5] ||
+        d.var->NST != config8[6] || sched != config8[7])
+      continue;
+    const TuneKey key = tune_key(*wfs, *A);
+    TuneEntry e{key, (int)(d.var - kVariants), d.TX, d.TY, d.NSLOT, d.sched, d.sync_every};
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (int i = 0; i < g_tune_n; ++i)
+      if (g_tune[i].key == key) {
+        g_tune[i] = e;
+        return SYNIM_OK;
+      }
+    if (g_tune_n < 256) g_tune[g_tune_n++] = e;
+    return SYNIM_OK;
+  }
+  return SYNIM_E_UNSUPPORTED;
 }
 
 extern "C" void synim_autotune_clear(void) {

@@ -198,5 +198,110 @@ def time_fit(ctx: Misreg, slopes, mode, reps=20, iter_cap=0):
     return float(np.median(ts)), float(ts[int(0.95 * (len(ts) - 1))])
 
 
+def evaluate(system: ProbeSystem, trained: Trained, seeds, batch: int = 1000,
+             max_iter: int = 20, timing_reps: int = 20) -> dict:
+    """Learned estimate against the Gauss-Newton fit on held-out seeds.
+
+    Every seed gives one noisy probe-slope sample (labels, SNR and noise drawn
+    from the seed).  Reported, per axis, in subapertures (shift / p) and as
+    pupil-edge displacement for rotation (rho * R) and magnification
+    ((m - 1) * R), R = pupil radius in subapertures:
+      * RMS of the MLP estimate minus the GN estimate (GN from theta0);
+      * RMS of each estimate minus the truth;
+      * GN iterations from theta0 and from the MLP estimate;
+      * median / p95 latency of one fit call at batch 1 and at ``batch``.
+    """
+    import torch
+    dev = system.probes.device
+    seeds = np.asarray(seeds)
+    n = len(seeds)
+    theta, snr, noise = draw(seeds, system.M)
+    gen = Misreg(system.wfs, system.probes, system.lo, system.hi, max_batch=batch)
+    slopes = synthesize(gen, theta, snr, noise, batch)
+    gen.close()
+    est = estimator(system, trained, max_batch=batch, max_iter=max_iter)
+    res = {MISREG_GN: [], MISREG_MLP: [], MISREG_MLP_GN: []}
+    its = {MISREG_GN: [], MISREG_MLP_GN: []}
+    for a in range(0, n, batch):
+        b = min(n, a + batch)
+        s = slopes[a:b].contiguous()
+        for mode in (MISREG_GN, MISREG_MLP, MISREG_MLP_GN):
+            th, it = est.infer(s, mode, use_graph=False)
+            res[mode].append(th.cpu().numpy())
+            if mode in its:
+                its[mode].append(it.cpu().numpy())
+    for k in res:
+        res[k] = np.concatenate(res[k])
+    for k in its:
+        its[k] = np.concatenate(its[k])
+    p = float(system.wfs.p)
+    radius = 0.5 * system.wfs.n_sub_x                     # pupil radius in subapertures
+    unit = np.array([1.0 / p, 1.0 / p, radius, radius])  # -> subapertures
+    shift = np.array([0.0, 0.0, 0.0, 1.0])
+
+    def rms(x, y):
+        d = ((x - shift) - (y - shift)) * unit
+        return [float(v) for v in np.sqrt(np.mean(d * d, axis=0))]
+
+    out = {
+        "n_samples": int(n),
+        "units": "subapertures (shift/p; rot*R; (mag-1)*R with R the pupil radius in subapertures)",
+        "rms_mlp_vs_gn": rms(res[MISREG_MLP], res[MISREG_GN]),
+        "rms_mlp_gn_vs_gn": rms(res[MISREG_MLP_GN], res[MISREG_GN]),
+        "rms_gn_vs_truth": rms(res[MISREG_GN], theta),
+        "rms_mlp_vs_truth": rms(res[MISREG_MLP], theta),
+        "gn_iters_mean": float(its[MISREG_GN].mean()),
+        "gn_iters_max": int(its[MISREG_GN].max()),
+        "mlp_gn_iters_mean": float(its[MISREG_MLP_GN].mean()),
+        "mlp_gn_iters_max": int(its[MISREG_MLP_GN].max()),
+        "gn_unconverged": int(np.sum(its[MISREG_GN] >= max_iter)),
+    }
+    timing = {}
+    for bsz in (1, min(batch, n)):
+        s = slopes[:bsz].contiguous()
+        for mode, name in ((MISREG_GN, "gn"), (MISREG_MLP, "mlp"), (MISREG_MLP_GN, "mlp_gn")):
+            med, p95 = time_fit(est, s, mode, reps=timing_reps)
+            timing[f"{name}_b{bsz}_ms"] = [med, p95]
+    out["latency_ms_median_p95"] = timing
+    est.close()
+    torch.cuda.synchronize(dev)
+    return out
+
+
+def run(n_train: int = 50_000, n_eval: int = 1000, epochs: int = 60, seed: int = 0,
+        log=None) -> dict:
+    """The whole learned-fit workload: synthesise the training set with the
+    library, train on the GPU kernels, evaluate on held-out seeds."""
+    import torch
+    t0 = time.perf_counter()
+    system = probe_system("cuda")
+    theta, snr, noise = draw(np.arange(n_train), system.M)
+    gen = Misreg(system.wfs, system.probes, system.lo, system.hi, max_batch=1000)
+    slopes = synthesize(gen, theta, snr, noise, 1000)
+    gen.close()
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    trained = train(system, slopes, theta, epochs=epochs, seed=seed, log=log)
+    rep = evaluate(system, trained, np.arange(1_000_000, 1_000_000 + n_eval))
+    rep.update({"n_train": n_train, "epochs_run": len(trained.history),
+                "train_seconds": trained.seconds, "data_seconds": t_data,
+                "final_val_mse": trained.history[-1][2] if trained.history else None})
+    return rep
+
+
 __all__ = ["ProbeSystem", "probe_system", "draw", "synthesize", "net_for", "he_init", "train",
-           "estimator", "time_fit", "MISREG_GN", "MISREG_MLP", "MISREG_MLP_GN"]
+           "estimator", "time_fit", "evaluate", "run", "MISREG_GN", "MISREG_MLP", "MISREG_MLP_GN"]
+
+
+if __name__ == "__main__":
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="train and evaluate the learned misregistration estimator")
+    ap.add_argument("--n-train", type=int, default=50_000)
+    ap.add_argument("--n-eval", type=int, default=1000)
+    ap.add_argument("--epochs", type=int, default=60)
+    args = ap.parse_args()
+    rep = run(args.n_train, args.n_eval, args.epochs,
+              log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(rep), flush=True)
