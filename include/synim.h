@@ -338,9 +338,14 @@ int synim_mlp_backward(const synim_mlp* net, const float* params, const float* x
                        float* scratch, const float* y, const float* t, float* grads,
                        float* loss, void* stream);
 
-/* One Adam step (bias-corrected, step >= 1) over n parameters, in place. */
+/* One Adam step (bias-corrected, step >= 1) over n parameters, in place:
+ *   m <- b1 m + (1-b1) g,  v <- b2 v + (1-b2) g^2,
+ *   p <- p - lr (m / (1-b1^step)) / (sqrt(v / (1-b2^step)) + eps).
+ * The hyperparameters are double so that 1-b1, 1-b2 and the bias
+ * corrections are exact before their single rounding to float.
+ * Errors: SYNIM_E_NULL, SYNIM_E_PARAM (step < 1, lr <= 0, b outside [0, 1)). */
 int synim_adam_step(float* params, const float* grads, float* m, float* v, size_t n, int step,
-                    float lr, float beta1, float beta2, float eps, void* stream);
+                    double lr, double beta1, double beta2, double eps, void* stream);
 
 /* ---------------------------------------------- misregistration estimation
  * Online tracking regenerates IMs from misregistration estimates (Sec. 5).
@@ -349,7 +354,9 @@ int synim_adam_step(float* params, const float* grads, float* m, float* v, size_
  *   S(theta) = slopes of the probes through the map of theta (as
  *              synim_im_build, one row of 2N per probe), J = dS/dtheta;
  *   Gauss-Newton theta <- theta + (J^T J)^-1 J^T (s - S(theta)) from
- *              theta0 = (0, 0, 0, 1), converged when |step / half-range| < tol;
+ *              theta0 = (0, 0, 0, 1), converged when |step / half-range| < tol
+ *              (S and J are FP32, which leaves a floor near 1e-7 on the
+ *              normalised step: use tol >= 1e-6);
  *   learned:   a synim_mlp (n_in = 2*feat_len -> h1 -> h2 -> 4) on the
  *              standardised features [x slopes | y slopes] (probe-major,
  *              subaperture-minor, each channel zero-padded to feat_len) whose
@@ -397,8 +404,9 @@ int synim_misreg_features(synim_misreg_ctx* c, const float* slopes, int B, const
  * captured per (B, mode, iter_cap) on `stream` (must not be NULL). */
 int synim_misreg_infer(synim_misreg_ctx* c, const float* slopes, int B, int mode, double* theta,
                        int32_t* iters, int iter_cap, int use_graph, void* stream);
-/* OR of the plan status words of the last GN run's plans (see
- * synim_plan_status); synchronises. */
+/* OR of the plan status words (see synim_plan_status) of the samples of the
+ * last synim_misreg_slopes or Gauss-Newton synim_misreg_infer call (0 after
+ * an MLP-only call); synchronises. */
 int synim_misreg_status(synim_misreg_ctx* c, int* host_out, void* stream);
 void synim_misreg_destroy(synim_misreg_ctx* c);
 

@@ -304,7 +304,7 @@ def im_config(wfs: Wfs, A) -> dict:
     return dict(zip(_CFG_KEYS, o[:8]))
 
 
-def im_candidates(wfs: Wfs, A, max_out: int = 96) -> list:
+def im_candidates(wfs: Wfs, A, max_out: int = 160) -> list:
     """Candidate kernel configurations in the autotuner's order."""
     lib = load()
     o = (C.c_int * (8 * max_out))()
@@ -498,7 +498,7 @@ class Misreg:
     :class:`Wfs`; ``lo``/``hi``: label box (shift x px, shift y px, rot rad,
     mag).  ``mlp`` = (Mlp, params, feat_mean, feat_std, feat_len) or None."""
 
-    def __init__(self, wfs: Wfs, probes, lo, hi, max_batch=1, max_iter=20, tol=1e-7,
+    def __init__(self, wfs: Wfs, probes, lo, hi, max_batch=1, max_iter=20, tol=1e-6,
                  kappa=1.0, mlp=None):
         torch = _torch()
         lib = load()

@@ -94,7 +94,8 @@ SIGNATURES = {
     "synim_mlp_scratch_floats": (SZ, [C.POINTER(SynimMlp), I]),
     "synim_mlp_forward": (I, [C.POINTER(SynimMlp), P, P, I, P, P, P]),
     "synim_mlp_backward": (I, [C.POINTER(SynimMlp), P, P, I, P, P, P, P, P, P]),
-    "synim_adam_step": (I, [P, P, P, P, SZ, I, C.c_float, C.c_float, C.c_float, C.c_float, P]),
+    "synim_adam_step": (I, [P, P, P, P, SZ, I, C.c_double, C.c_double, C.c_double, C.c_double,
+                            P]),
     "synim_misreg_workspace": (I, [C.POINTER(SynimMisregDesc), C.POINTER(SZ)]),
     "synim_misreg_create": (I, [C.POINTER(SynimMisregDesc), P, SZ, P, C.POINTER(P)]),
     "synim_misreg_slopes": (I, [P, P, I, P, P, P]),

@@ -419,16 +419,24 @@ __device__ __forceinline__ void wait_vm(int n) {
   }
 }
 
-// Coherent read of a counter that other workgroups update with device-scope
-// atomics: a scalar load that misses the scalar cache (glc), waited on the
-// LGKM counter so that the vector-memory pipeline of the wave is untouched.
-__device__ __forceinline__ int load_counter(const int* p) {
-  int v;
-  asm volatile("s_load_dword %0, %1, 0x0 glc\n\ts_waitcnt lgkmcnt(0)" : "=s"(v) : "s"(p) : "memory");
-  return v;
-}
+// XCD sync bookkeeping.  The block-entry counter of a workgroup's XCD is read
+// in two ways:
+//  * a snapshot that rides with every stage: a 4-byte buffer->LDS DMA of the
+//    counter issued just before the stage's IF rows, so the wait that makes
+//    the stage visible also makes the snapshot visible, at no extra stall;
+//    the load has device scope (sc1, as an agent-scope atomic load), so it
+//    sees the other workgroups' atomics;
+//  * a device-scope atomic load, only when a snapshot says the peers are
+//    behind (the wave then waits for it, draining its own DMA queue).
+constexpr int SNAP_AUX = 16;          // sc1: device scope
+constexpr int SYNC_SPIN_MAX = 1000;   // polls before a workgroup stops syncing
+constexpr int SYNC_STRIDE = 32;       // ints between the counters (own 128-byte line)
 
-constexpr int SYNC_SPIN_MAX = 4000;   // polls before a workgroup stops syncing
+__device__ __forceinline__ void snapshot_issue(const int* ctr, int* lds_dst) {
+  __amdgpu_buffer_rsrc_t r =
+      __builtin_amdgcn_make_buffer_rsrc(const_cast<int*>(ctr), (short)0, 4, 0x00020000);
+  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)lds_dst, 4, 0, 0, 0, SNAP_AUX);
+}
 
 // Persistent streaming kernel.  Work items are (actuator chunk, tile) pairs;
 // workgroup b serves the queue of its XCD (b mod 8 - consecutive workgroups are
@@ -445,6 +453,7 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
   static_assert(NJ * (NST - 2) <= 63, "vmcnt range");
   __shared__ int s_item;
   __shared__ double s_red[BLOCK / 64];
+  __shared__ int s_snap[NST];   // per stage: block-entry counter when it was issued
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
@@ -550,7 +559,7 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
     // XCD sync (single pair only; E >= NST - 1 is guaranteed by the host)
     const bool sync_on = g.pairs == nullptr && g.sync_every > 0;
     const int sync_e = sync_on ? g.sync_every : 1;
-    int* sync_ctr = g.sync_ctr + 8 * blockIdx.z + xcd;
+    int* sync_ctr = g.sync_ctr + (8 * blockIdx.z + xcd) * SYNC_STRIDE;
     const int n_part = sync_on ? *g.n_active : 0;
     bool sync_live = true;
 
@@ -582,7 +591,14 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
         __builtin_nontemporal_store(q == 0 ? sx : sy, dst);
       }
     };
-    auto issue = [&](float4* buf, int a) {
+    // Loads actuator a into stage k.  With the XCD sync on, lane 0 first adds
+    // the workgroup's entry when a opens a block, then snapshots the counter
+    // into s_snap[k]; both precede the stage's DMA.
+    auto issue = [&](int k, float4* buf, int a) {
+      if (sync_on && tid == 0) {
+        if ((a - a0) % sync_e == 0) atomicAdd(sync_ctr, 1);
+        snapshot_issue(sync_ctr, s_snap + k);
+      }
       stage_issue<BLOCK, NJ, VW>(P.ifs + (size_t)a * plane_in, plane_bytes, voff, buf, wave);
     };
     // one pipeline step for actuator a held in stage K: wait for it (the later
@@ -596,48 +612,47 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
     // of each step since then.
     //
     // With the XCD sync on, actuator a0 + j with j a multiple of E opens
-    // block j/E: wave 0 first waits (bounded) until the XCD's block-entry
-    // counter shows that every tile entered block j/E - 1, then lane 0 adds
-    // its own entry right before the block's first DMA.  Those atomics are
-    // vector-memory operations of wave 0, so wave 0's wait also counts the
-    // entries issued after this stage's DMA (E >= NST - 1 keeps the prologue
-    // free of entries other than block 0).  A workgroup that waits too long
-    // stops waiting but keeps adding its entries, so the counts stay exact.
+    // block j/E, and a workgroup may open block b >= 1 only once every tile
+    // of its XCD has opened block b - 1 (counter >= b * n_part).  Wave 0
+    // checks the snapshot that came with the stage just waited for; only if
+    // that is short does it poll the counter itself (bounded: a workgroup
+    // that waits too long stops waiting but keeps adding its entries, so the
+    // counts stay exact).  Wave 0 also issues, per loaded actuator, the
+    // snapshot and possibly an entry atomic; its wait counts them.
     auto step = [&](auto kc, int a) {
       constexpr int K = decltype(kc)::value;
       const int later = min(NST - 2, a1 - 1 - a);
       const int stores = VJP ? 0 : min(a - a0, NST - 1);
       const int x = a + NST - 1;   // the actuator this step starts loading
       int extra = 0;
-      if (sync_on) {
-        const int jx = x - a0;
-        if (wave == 0 && sync_live && x < a1 && jx > 0 && jx % sync_e == 0) {
-          const int target = (jx / sync_e) * n_part;
-          int it = 0;
-          while (load_counter(sync_ctr) < target) {
-            if (++it >= SYNC_SPIN_MAX) {
-              sync_live = false;
-              break;
-            }
-            __builtin_amdgcn_s_sleep(2);
-          }
-        }
-        if (wave == 0) {
-          const int j = a - a0;
-          extra = (j + later) / sync_e - j / sync_e;
-        }
+      if (sync_on && wave == 0) {
+        const int j = a - a0;
+        extra = later + (j + later) / sync_e - j / sync_e;
       }
       wait_vm(later * NJ + stores + extra);
-      __builtin_amdgcn_s_barrier();
-      if (x < a1) {
-        if (sync_on && tid == 0 && (x - a0) % sync_e == 0) atomicAdd(sync_ctr, 1);
-        issue(stage_buf<(K + NST - 1) % NST, STAGE_F4>(), x);
+      if (sync_on && wave == 0 && sync_live && x < a1) {
+        const int jx = x - a0;
+        if (jx > 0 && jx % sync_e == 0) {
+          const int target = (jx / sync_e) * n_part;
+          if (s_snap[K] < target) {
+            int it = 0;
+            while (__hip_atomic_load(sync_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                   target) {
+              if (++it >= SYNC_SPIN_MAX) {
+                sync_live = false;
+                break;
+              }
+              __builtin_amdgcn_s_sleep(4);
+            }
+          }
+        }
       }
+      __builtin_amdgcn_s_barrier();
+      if (x < a1) issue((K + NST - 1) % NST, stage_buf<(K + NST - 1) % NST, STAGE_F4>(), x);
       consume(stage_buf<K, STAGE_F4>(), a);
     };
-    if (sync_on && tid == 0 && a0 < a1) atomicAdd(sync_ctr, 1);   // block 0
     [&]<int... K>(std::integer_sequence<int, K...>) {
-      ((a0 + K < a1 && K < NST - 1 ? issue(stage_buf<K, STAGE_F4>(), a0 + K) : void()), ...);
+      ((a0 + K < a1 && K < NST - 1 ? issue(K, stage_buf<K, STAGE_F4>(), a0 + K) : void()), ...);
     }(std::make_integer_sequence<int, NST>{});
     for (int a = a0; a < a1; a += NST) {
       [&]<int... K>(std::integer_sequence<int, K...>) {
@@ -740,6 +755,9 @@ struct WsLayout {
 };
 
 constexpr int MAX_PLANES = 5;
+// Counter ints of a plan: 8 work-item counters per plane, then one XCD sync
+// counter per plane and XCD, each on its own 128-byte line.
+constexpr int COUNTER_INTS = 8 * MAX_PLANES + 8 * MAX_PLANES * 32;
 
 // Patch size (columns, rows) a map needs for subapertures of p pixels: the
 // haloed subaperture spans (p+1) output pixels, which the map stretches by
@@ -832,9 +850,10 @@ int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double*
         // sync blocks of E actuators: E >= NST - 1 keeps the pipeline
         // prologue free of block entries
         const int e_min = std::max(2, v.NST - 1);
-        const int es[3] = {e_min, std::max(8, e_min), 0};
-        const double f[3] = {0.85, 0.87, 0.9};
-        for (int q = 0; q < 3; ++q) {
+        const int es[4] = {e_min, std::max(4, e_min), std::max(8, e_min), 0};
+        const double f[4] = {0.85, 0.86, 0.87, 0.9};
+        for (int q = 0; q < 4; ++q) {
+          if (q > 0 && q < 3 && es[q] == es[q - 1]) continue;
           Dims d = tmp[k];
           d.sched = SCHED_XCD;
           d.sync_every = es[q];
@@ -855,7 +874,7 @@ int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double*
   return n;
 }
 
-constexpr int MAX_CAND = 96;
+constexpr int MAX_CAND = 160;
 
 // Autotune cache: geometry key -> (variant, tile shape) measured fastest.
 struct TuneKey {
@@ -912,7 +931,7 @@ WsLayout layout(const synim_wfs& w, const Dims& d, int planes) {
   };
   const size_t nv = (size_t)w.n_valid;
   L.status = take(16 * sizeof(int));
-  L.counters = take(16 * MAX_PLANES * sizeof(int));   // work items, then sync blocks
+  L.counters = take(COUNTER_INTS * sizeof(int));   // work items, then sync blocks
   L.scratch = take(64 * sizeof(float));
   L.origin = take(nv * sizeof(int2));
   L.inv2nk = take(nv * sizeof(double));
@@ -1133,7 +1152,8 @@ int launch_stream(const Plan& P, const float* ifs, int n_act, int H_in, int W_in
   g.sync_every = d.sched == SCHED_XCD ? d.sync_every : 0;
   g.sync_ctr = P.counters() + 8 * MAX_PLANES;
   g.n_active = P.status() + 1;
-  hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(128), 0, st, P.counters(), 16 * MAX_PLANES);
+  hipLaunchKernelGGL(zero_ints_kernel, dim3((COUNTER_INTS + 255) / 256), dim3(256), 0, st,
+                     P.counters(), COUNTER_INTS);
   SYNIM_HIP_TRY(hipGetLastError());
   hipLaunchKernelGGL(fn, dim3((unsigned)G, 1, nplanes), dim3(v.BLOCK), 0, st, g);
   SYNIM_HIP_TRY(hipGetLastError());

@@ -167,17 +167,20 @@ __global__ void mse_grad_kernel(const float* __restrict__ y, const float* __rest
   if (threadIdx.x == 0 && loss) *loss = red[0] * scale;
 }
 
+// One Adam step.  The coefficients come from the host, formed in double from
+// the double hyperparameters (1 - beta2 in float would lose five digits).
 __global__ void adam_kernel(float* __restrict__ p, const float* __restrict__ g,
                             float* __restrict__ m, float* __restrict__ v, long n, float lr,
-                            float b1, float b2, float eps, float c1, float c2) {
+                            float b1, float omb1, float b2, float omb2, float eps, float inv_c1,
+                            float inv_c2) {
   const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
-  const float mi = b1 * m[i] + (1.f - b1) * gi;
-  const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+  const float mi = b1 * m[i] + omb1 * gi;
+  const float vi = b2 * v[i] + omb2 * (gi * gi);
   m[i] = mi;
   v[i] = vi;
-  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  p[i] -= lr * (mi * inv_c1) / (sqrtf(vi * inv_c2) + eps);
 }
 
 __global__ void scatter_cols_kernel(const float* __restrict__ src, int N, int K, int seg0,
@@ -390,16 +393,19 @@ extern "C" int synim_mlp_backward(const synim_mlp* net, const float* params, con
 }
 
 extern "C" int synim_adam_step(float* params, const float* grads, float* m, float* v, size_t n,
-                               int step, float lr, float beta1, float beta2, float eps,
+                               int step, double lr, double beta1, double beta2, double eps,
                                void* stream) {
   if (!params || !grads || !m || !v) return SYNIM_E_NULL;
-  if (step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1))
+  if (step < 1 || !(lr > 0) || !(beta1 >= 0 && beta1 < 1) || !(beta2 >= 0 && beta2 < 1) ||
+      !(eps >= 0))
     return SYNIM_E_PARAM;
-  const float c1 = 1.f - std::pow(beta1, (float)step);
-  const float c2 = 1.f - std::pow(beta2, (float)step);
+  if (n == 0) return SYNIM_OK;
+  const double c1 = 1.0 - std::pow(beta1, (double)step);
+  const double c2 = 1.0 - std::pow(beta2, (double)step);
   hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0,
-                     (hipStream_t)stream, params, grads, m, v, (long)n, lr, beta1, beta2, eps, c1,
-                     c2);
+                     (hipStream_t)stream, params, grads, m, v, (long)n, (float)lr, (float)beta1,
+                     (float)(1.0 - beta1), (float)beta2, (float)(1.0 - beta2), (float)eps,
+                     (float)(1.0 / c1), (float)(1.0 / c2));
   SYNIM_HIP_TRY(hipGetLastError());
   return SYNIM_OK;
 }

@@ -115,9 +115,12 @@ class Trained:
     seconds: float
 
 
-def train(system: ProbeSystem, slopes, theta, *, feat_len=4000, epochs=40, batch=256, lr=1e-3,
-          seed=0, val_frac=0.1, patience=6, log=None) -> Trained:
-    """Train the estimator on (noisy slopes [n][M] GPU, theta [n][4] numpy)."""
+def train(system: ProbeSystem, slopes, theta, *, feat_len=4000, epochs=60, batch=256, lr=1e-3,
+          lr_min=1e-5, seed=0, val_frac=0.1, patience=12, log=None) -> Trained:
+    """Train the estimator on (noisy slopes [n][M] GPU, theta [n][4] numpy).
+
+    Adam with a cosine learning-rate decay from ``lr`` to ``lr_min`` over the
+    epochs; the parameters with the best validation MSE are kept."""
     import torch
     dev = slopes.device
     net = net_for(system, feat_len)
@@ -155,7 +158,9 @@ def train(system: ProbeSystem, slopes, theta, *, feat_len=4000, epochs=40, batch
             net.forward(params, xb, scratch, out)
             net.backward(params, xb, scratch, out, yb, grads, loss)
             step += 1
-            adam_step(params, grads, m, v, step, lr=lr)
+            t = step / float(max(1, epochs * nb))
+            adam_step(params, grads, m, v, step,
+                      lr=lr_min + 0.5 * (lr - lr_min) * (1.0 + math.cos(math.pi * min(1.0, t))))
             tot += float(loss.item()) if k == nb - 1 else 0.0
         yv = net.forward(params, x[n_tr:].contiguous(), vscratch)
         vl = float(((yv - y[n_tr:]) ** 2).mean().item())

@@ -196,3 +196,41 @@ def test_elt_full_size_sampled_columns(S):
     ref = oim.im_build(Fs, A[:, :2], A[:, 2], cfg.pupil, 6, cfg.valid)
     assert rel_err(got, ref) <= IM_TOL, rel_err(got, ref)
     del Fd
+
+
+def test_autograd_function_backward(S):
+    """interaction_matrix(theta) through torch.autograd: the backward pass is
+    the VJP kernel; checked against the oracle's Jacobian contraction and
+    against FP64 central differences of the oracle's inner product."""
+    import torch
+    from paper_2606_07759_amd.autograd import interaction_matrix
+    cfg = wl.scao_small()
+    F = wl.if_stack(cfg.grid)
+    Fd = to_dev(F)
+    wfs = S.Wfs.from_numpy(cfg.pupil, 10, cfg.valid)
+    G = np.random.default_rng(5).standard_normal((81, 2 * cfg.n_valid)).astype(np.float32)
+    theta = torch.tensor(cfg.theta, dtype=torch.float64, requires_grad=True)
+    im = interaction_matrix(theta, Fd, wfs)
+    loss = (im * to_dev(G)).sum()
+    loss.backward()
+    got = theta.grad.numpy()
+    Jr = oim.jacobian(F, cfg.theta, cfg.pupil, 10, cfg.valid)
+    ref = oim.vjp(G, Jr)
+    for j in range(4):
+        scale = np.sum(np.abs(G) * np.abs(Jr[j]))
+        assert abs(got[j] - ref[j]) <= J_TOL * scale, (j, got[j], ref[j])
+    # FP64 central differences of <G, IM(theta)> (oracle), step 1e-6
+    G64 = G.astype(np.float64)
+    for j in range(4):
+        h = 1e-6
+        tp = np.array(cfg.theta, dtype=np.float64)
+        tm = tp.copy()
+        tp[j] += h
+        tm[j] -= h
+        fd = ((G64 * oim.im_build_misreg(F, tp, cfg.pupil, 10, cfg.valid)).sum()
+              - (G64 * oim.im_build_misreg(F, tm, cfg.pupil, 10, cfg.valid)).sum()) / (2 * h)
+        scale = np.sum(np.abs(G) * np.abs(Jr[j]))
+        assert abs(got[j] - fd) <= J_TOL * scale, (j, got[j], fd)
+    # the forward value is the plain IM build
+    ref_im = oim.im_build_misreg(F, cfg.theta, cfg.pupil, 10, cfg.valid)
+    assert rel_err(im.detach().cpu().numpy(), ref_im) <= IM_TOL
