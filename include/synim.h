@@ -381,6 +381,10 @@ typedef struct {
   int32_t h1, h2, feat_len;   /* hidden sizes; per-channel input length         */
   const float* feat_mean;     /* device [2 n_probe N] feature mean              */
   const float* feat_std;      /* device [2 n_probe N] feature std (> 0)         */
+  int32_t gn_batched;         /* 0: Gauss-Newton in one launch per call when the
+                                 WFS is small (n_probe*N <= 65536, p <= 64), else
+                                 per iteration through the batched 5-plane build;
+                                 1: always the batched build                    */
 } synim_misreg_desc;
 
 typedef struct synim_misreg_ctx synim_misreg_ctx;
@@ -405,8 +409,9 @@ int synim_misreg_features(synim_misreg_ctx* c, const float* slopes, int B, const
 int synim_misreg_infer(synim_misreg_ctx* c, const float* slopes, int B, int mode, double* theta,
                        int32_t* iters, int iter_cap, int use_graph, void* stream);
 /* OR of the plan status words (see synim_plan_status) of the samples of the
- * last synim_misreg_slopes or Gauss-Newton synim_misreg_infer call (0 after
- * an MLP-only call); synchronises. */
+ * last synim_misreg_slopes call or batched Gauss-Newton synim_misreg_infer
+ * call (0 after an MLP-only or one-launch Gauss-Newton call, which build no
+ * plans); synchronises. */
 int synim_misreg_status(synim_misreg_ctx* c, int* host_out, void* stream);
 void synim_misreg_destroy(synim_misreg_ctx* c);
 

@@ -499,7 +499,7 @@ class Misreg:
     mag).  ``mlp`` = (Mlp, params, feat_mean, feat_std, feat_len) or None."""
 
     def __init__(self, wfs: Wfs, probes, lo, hi, max_batch=1, max_iter=20, tol=1e-6,
-                 kappa=1.0, mlp=None):
+                 kappa=1.0, mlp=None, gn_batched=False):
         torch = _torch()
         lib = load()
         self.wfs = wfs
@@ -516,6 +516,7 @@ class Misreg:
             d.theta_hi[j] = float(hi[j])
         d.max_iter = int(max_iter)
         d.tol = float(tol)
+        d.gn_batched = 1 if gn_batched else 0
         if mlp is not None:
             net, params, mean, std, feat_len = mlp
             d.mlp_params = params.data_ptr()

@@ -47,7 +47,8 @@ class SynimMisregDesc(C.Structure):
                 ("max_batch", C.c_int32), ("theta_lo", C.c_double * 4),
                 ("theta_hi", C.c_double * 4), ("max_iter", C.c_int32), ("tol", C.c_double),
                 ("mlp_params", C.c_void_p), ("h1", C.c_int32), ("h2", C.c_int32),
-                ("feat_len", C.c_int32), ("feat_mean", C.c_void_p), ("feat_std", C.c_void_p)]
+                ("feat_len", C.c_int32), ("feat_mean", C.c_void_p), ("feat_std", C.c_void_p),
+                ("gn_batched", C.c_int32)]
 
 
 P = C.c_void_p

@@ -825,8 +825,9 @@ int persistent_grid(StreamFn fn, int block);
 
 // Every (variant, tile shape, schedule) that can run this geometry with the
 // smallest weight patch that fits, cheapest first by the cost model.  The
-// one-chunk-per-XCD schedule is offered for tile shapes with no more tiles
-// than an XCD has resident workgroups (known only with a device present).
+// one-chunk-per-XCD schedule is offered for tile shapes with at most 5/4 as
+// many tiles as an XCD has resident workgroups (known only with a device
+// present).
 int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double* cost_out,
                    int max_out) {
   int pw_need, ph_need;
@@ -846,7 +847,9 @@ int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double*
     const int G = persistent_grid(v.im4, v.BLOCK);
     for (int k = 0; k < m; ++k) {
       all.push_back({tc[k], tmp[k]});
-      if (G >= 8 && tmp[k].n_tiles <= G / 8) {
+      // empty tiles (outside the pupil) are skipped at once, so a few more
+      // tiles than resident workgroups still start together
+      if (G >= 8 && 4 * tmp[k].n_tiles <= 5 * (G / 8)) {
         // sync blocks of E actuators: E >= NST - 1 keeps the pipeline
         // prologue free of block entries
         const int e_min = std::max(2, v.NST - 1);

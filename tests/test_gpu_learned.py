@@ -194,17 +194,19 @@ def test_misreg_slopes_and_jacobian_parity(gpu_lib, probe):
     ctx.close()
 
 
-def test_gn_recovers_noise_free(gpu_lib, probe):
+@pytest.mark.parametrize("batched", [False, True], ids=["fused", "batched"])
+def test_gn_recovers_noise_free(gpu_lib, probe, batched):
     import torch
     S = gpu_lib
     pc, wfs, maps = probe
     cfg = pc.scao
-    say("[case] GN noise-free")
+    say(f"[case] GN noise-free batched={batched}")
     truth = np.array(THETAS[1:] + [(1.2, 0.4, math.radians(0.2), 1.004)])
     F = pc.probe_maps.astype(np.float64)
     meas = np.stack([omr.probe_slopes(F, t, cfg.pupil, cfg.p, cfg.valid).ravel()
                      for t in truth]).astype(np.float32)
-    ctx = S.Misreg(wfs, maps, wl.LABEL_LO, wl.LABEL_HI, max_batch=8, max_iter=30)
+    ctx = S.Misreg(wfs, maps, wl.LABEL_LO, wl.LABEL_HI, max_batch=8, max_iter=30,
+                   gn_batched=batched)
     for graph in (False, True):
         th, it = ctx.infer(torch.from_numpy(meas).cuda(), S.MISREG_GN, use_graph=graph)
         th = th.cpu().numpy()
@@ -217,12 +219,13 @@ def test_gn_recovers_noise_free(gpu_lib, probe):
     ctx.close()
 
 
-def test_gn_matches_oracle_on_noisy_slopes(gpu_lib, probe):
+@pytest.mark.parametrize("batched", [False, True], ids=["fused", "batched"])
+def test_gn_matches_oracle_on_noisy_slopes(gpu_lib, probe, batched):
     import torch
     S = gpu_lib
     pc, wfs, maps = probe
     cfg = pc.scao
-    say("[case] GN noisy vs oracle GN")
+    say(f"[case] GN noisy vs oracle GN batched={batched}")
     F = pc.probe_maps.astype(np.float64)
     scale = 0.5 * (wl.LABEL_HI - wl.LABEL_LO)
     meas, refs = [], []
@@ -234,7 +237,8 @@ def test_gn_matches_oracle_on_noisy_slopes(gpu_lib, probe):
         ref, _, ok = omr.gauss_newton(meas[-1].astype(np.float64), F, cfg.pupil, cfg.p,
                                       cfg.valid, scale, max_iter=30)
         refs.append(ref)
-    ctx = S.Misreg(wfs, maps, wl.LABEL_LO, wl.LABEL_HI, max_batch=2, max_iter=30)
+    ctx = S.Misreg(wfs, maps, wl.LABEL_LO, wl.LABEL_HI, max_batch=2, max_iter=30,
+                   gn_batched=batched)
     th, it = ctx.infer(torch.from_numpy(np.stack(meas)).cuda(), S.MISREG_GN)
     th = th.cpu().numpy()
     refs = np.array(refs)
