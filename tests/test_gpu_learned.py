@@ -247,3 +247,34 @@ def test_gn_matches_oracle_on_noisy_slopes(gpu_lib, probe, batched):
     assert np.all(np.abs(th[:, 2] - refs[:, 2]) <= 5e-5)
     assert np.all(np.abs(th[:, 3] - refs[:, 3]) <= 5e-5)
     ctx.close()
+
+
+def test_gn_large_grid_global_taps(gpu_lib):
+    """A WFS whose probe footprint does not fit in LDS (12x12 subapertures of
+    10 px, 4 smooth probe maps on 160^2): the one-launch Gauss-Newton reads its
+    taps from global memory; noise-free slopes give back theta, noisy ones the
+    oracle's fit."""
+    import torch
+    S = gpu_lib
+    say("[case] GN large grid")
+    pup = wl.pupil_mask(120, 120.0, 0.2)
+    val = wl.valid_subapertures(pup, 10)
+    c = (160 - 1) / 2.0
+    yy, xx = np.mgrid[0:160, 0:160].astype(np.float64)
+    maps = []
+    for (ax, ay, sg) in ((0.0, 0.0, 30.0), (25.0, -10.0, 18.0), (-20.0, 22.0, 22.0), (5.0, 30.0, 15.0)):
+        maps.append(np.exp(-((xx - c - ax) ** 2 + (yy - c - ay) ** 2) / (2 * sg * sg)))
+    maps = np.stack(maps).astype(np.float32)
+    F = maps.astype(np.float64)
+    lo = np.array([-5.0, -5.0, math.radians(-1.0), 0.98])
+    hi = np.array([5.0, 5.0, math.radians(1.0), 1.02])
+    truth = np.array([(2.3, -1.7, math.radians(0.4), 1.008), (-4.1, 3.3, math.radians(-0.7), 0.985)])
+    meas = np.stack([omr.probe_slopes(F, t, pup, 10, val).ravel() for t in truth]).astype(np.float32)
+    wfs = S.Wfs.from_numpy(pup, 10, val, device="cuda:0")
+    ctx = S.Misreg(wfs, torch.from_numpy(maps).cuda(), lo, hi, max_batch=2, max_iter=30)
+    th, it = ctx.infer(torch.from_numpy(meas).cuda(), S.MISREG_GN)
+    th = th.cpu().numpy()
+    say("theta", th, "iters", it.cpu().numpy())
+    assert np.all(np.abs(th[:, :2] - truth[:, :2]) <= 2e-3)
+    assert np.all(np.abs(th[:, 2:] - truth[:, 2:]) <= 2e-5)
+    ctx.close()
