@@ -65,6 +65,7 @@ struct PlanJob {
   int TX, TY, NSLOT, n_tiles_x;
   int n_tiles, BHmax, pad0, pad1;
   int2* origin;
+  int2* hrows;                // [nv] patch rows [x, y) holding a non-zero weight
   double* inv2nk;
   float* weights;             // [plane][kk][x|y][PH*PW]
   int* slot_kk;               // [tile][NSLOT]
@@ -112,6 +113,7 @@ __global__ void plan_subaps_kernel(PlanJob one, const PlanJob* __restrict__ jobs
   }
   if (nk == 0) atomicOr(J.status, 4);
   J.origin[kk] = make_int2(ox, oy);
+  J.hrows[kk] = make_int2(J.PH, 0);   // narrowed by plan_weights
   J.inv2nk[kk] = nk > 0 ? 1.0 / (2.0 * nk) : 0.0;
 }
 
@@ -188,6 +190,12 @@ __global__ void plan_weights_kernel(PlanJob one, const PlanJob* __restrict__ job
       }
     }
   const double s = J.inv2nk[kk];
+  bool used = false;
+  for (int j = 0; j < J.n_planes; ++j) used = used || acc[j][0] != 0.0 || acc[j][1] != 0.0;
+  if (used) {
+    atomicMin(&J.hrows[kk].x, r);
+    atomicMax(&J.hrows[kk].y, r + 1);
+  }
   for (int j = 0; j < J.n_planes; ++j) {
     float* w = J.weights + ((size_t)j * J.nv + kk) * 2 * E;
     w[e] = (float)(acc[j][0] * s);
@@ -227,7 +235,7 @@ __global__ void plan_slots_kernel(PlanJob one, const PlanJob* __restrict__ jobs)
 __global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
                                                         const PlanJob* __restrict__ jobs) {
   const PlanJob& J = job_of(one, jobs);
-  __shared__ int s_ox[1024], s_oy[1024];
+  __shared__ int s_ox[1024], s_oy[1024], s_oe[1024];
   __shared__ int s_x0[MAX_TILE_ROWS], s_w[MAX_TILE_ROWS];
   __shared__ int s_ymin, s_ymax;
   const int t = blockIdx.x, tid = threadIdx.x;
@@ -240,14 +248,22 @@ __global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
   __syncthreads();
   for (int s = tid; s < NS; s += blockDim.x) {
     const int kk = J.slot_kk[(size_t)t * NS + s];
-    int2 o = make_int2(INT_MIN, INT_MIN);
+    // rows [oy, oe) of the IF grid that the subaperture's weights touch
+    int ox = INT_MIN, oy = INT_MIN, oe = INT_MIN;
     if (kk >= 0) {
-      o = J.origin[kk];
-      atomicMin(&s_ymin, o.y);
-      atomicMax(&s_ymax, o.y);
+      const int2 o = J.origin[kk];
+      const int2 hr = J.hrows[kk];
+      if (hr.x < hr.y) {
+        ox = o.x;
+        oy = o.y + hr.x;
+        oe = o.y + hr.y;
+        atomicMin(&s_ymin, oy);
+        atomicMax(&s_ymax, oe);
+      }
     }
-    s_ox[s] = o.x;
-    s_oy[s] = o.y;
+    s_ox[s] = ox;
+    s_oy[s] = oy;
+    s_oe[s] = oe;
   }
   __syncthreads();
   const int y0 = s_ymin;
@@ -255,7 +271,7 @@ __global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
     if (tid == 0) J.tile_info[t] = make_int4(0, 0, 0, 0);
     return;
   }
-  const int bh = s_ymax + PH - y0;
+  const int bh = s_ymax - y0;
   if (bh > J.BHmax || bh > MAX_TILE_ROWS) {
     if (tid == 0) {
       atomicOr(J.status, 2);
@@ -268,7 +284,7 @@ __global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
     int lo = INT_MAX, hi = INT_MIN;
     for (int s = 0; s < NS; ++s) {
       const int oy = s_oy[s];
-      if (oy != INT_MIN && oy <= y && y < oy + PH) {
+      if (oy != INT_MIN && oy <= y && y < s_oe[s]) {
         lo = min(lo, s_ox[s]);
         hi = max(hi, s_ox[s] + PW);
       }
@@ -326,6 +342,7 @@ struct PairDesc {
   const float* ifs;          // [n_act][H_in][W_in]
   float* out;                // plane (out_plane0) of [plane][n_act][2nv]
   const int2* origin;
+  const int2* hrows;         // patch rows holding a non-zero weight
   const float* weights;      // plane 0 base
   const int* slot_kk;
   const int4* tile_info;
@@ -515,11 +532,18 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
     int base[RPL];
     if (kk >= 0) {
       const int2 o = P.origin[kk];
+      const int2 hr = P.hrows[kk];
       const float* W = P.weights + ((size_t)plane * P.nv + kk) * 2 * E;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
-        const int2 rw = rows[o.y - y0 + q + LPS * i];
-        base[i] = rw.y + (o.x - rw.x);
+        // patch rows outside [hr.x, hr.y) hold zero weights and are not
+        // staged: point them at any staged float (all are finite)
+        const int pr = q + LPS * i;
+        base[i] = 0;
+        if (pr >= hr.x && pr < hr.y) {
+          const int2 rw = rows[o.y + pr - y0];
+          base[i] = rw.y + (o.x - rw.x);
+        }
 #pragma unroll
         for (int c = 0; c < PW; ++c) {
           wx[i][c] = W[(q + LPS * i) * PW + c];
@@ -717,6 +741,8 @@ constexpr int nst_vw1(int n, int s) { return s < 2 + 63 / (4 * n) ? s : 2 + 63 /
 // deeper pipelines of one workgroup per CU keep more bytes in flight.
 const Variant kVariants[] = {
     SYNIM_VARIANT(1024, 4, 2, 8, 3, 3),  SYNIM_VARIANT(512, 4, 2, 8, 3, 6),
+    SYNIM_VARIANT(512, 4, 2, 8, 3, 3),   SYNIM_VARIANT(512, 4, 3, 10, 3, 3),
+    SYNIM_VARIANT(512, 4, 3, 12, 3, 3),
     SYNIM_VARIANT(256, 4, 2, 8, 4, 3),   SYNIM_VARIANT(256, 4, 2, 8, 4, 8),
     SYNIM_VARIANT(1024, 4, 3, 10, 3, 3), SYNIM_VARIANT(512, 4, 3, 10, 3, 6),
     SYNIM_VARIANT(512, 4, 3, 10, 2, 8),  SYNIM_VARIANT(256, 4, 3, 10, 4, 3),
@@ -724,6 +750,8 @@ const Variant kVariants[] = {
     SYNIM_VARIANT(1024, 4, 3, 12, 3, 3), SYNIM_VARIANT(512, 4, 3, 12, 3, 6),
     SYNIM_VARIANT(256, 4, 3, 12, 4, 3),
     SYNIM_VARIANT(512, 8, 2, 12, 3, 6),  SYNIM_VARIANT(256, 8, 2, 12, 6, 3),
+    SYNIM_VARIANT(1024, 8, 2, 14, 3, 3), SYNIM_VARIANT(512, 8, 2, 14, 3, 3),
+    SYNIM_VARIANT(1024, 8, 2, 16, 3, 3),
     SYNIM_VARIANT(512, 8, 2, 14, 3, 6),  SYNIM_VARIANT(256, 8, 2, 14, 6, 3),
     SYNIM_VARIANT(512, 8, 2, 16, 3, 6),  SYNIM_VARIANT(256, 8, 2, 16, 6, 3),
     SYNIM_VARIANT(256, 8, 3, 20, 6, 3),  SYNIM_VARIANT(256, 8, 3, 24, 6, 3),
@@ -750,8 +778,8 @@ struct Dims {
 };
 
 struct WsLayout {
-  size_t status, counters, scratch, origin, inv2nk, weights, slot_kk, tile_info, rows, partials,
-      total;
+  size_t status, counters, scratch, origin, hrows, inv2nk, weights, slot_kk, tile_info, rows,
+      partials, total;
 };
 
 constexpr int MAX_PLANES = 5;
@@ -937,6 +965,7 @@ WsLayout layout(const synim_wfs& w, const Dims& d, int planes) {
   L.counters = take(COUNTER_INTS * sizeof(int));   // work items, then sync blocks
   L.scratch = take(64 * sizeof(float));
   L.origin = take(nv * sizeof(int2));
+  L.hrows = take(nv * sizeof(int2));
   L.inv2nk = take(nv * sizeof(double));
   L.weights = take((size_t)planes * nv * 2 * d.PH * d.PW * sizeof(float));
   L.slot_kk = take((size_t)d.n_tiles * d.NSLOT * sizeof(int));
@@ -955,6 +984,7 @@ struct Plan {
   int* counters() const { return reinterpret_cast<int*>(ws + L.counters); }
   float* scratch() const { return reinterpret_cast<float*>(ws + L.scratch); }
   int2* origin() const { return reinterpret_cast<int2*>(ws + L.origin); }
+  int2* hrows() const { return reinterpret_cast<int2*>(ws + L.hrows); }
   double* inv2nk() const { return reinterpret_cast<double*>(ws + L.inv2nk); }
   float* weights() const { return reinterpret_cast<float*>(ws + L.weights); }
   int* slot_kk() const { return reinterpret_cast<int*>(ws + L.slot_kk); }
@@ -1028,6 +1058,7 @@ PlanJob make_job(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map
   J.n_tiles = d.n_tiles;
   J.BHmax = d.BHmax;
   J.origin = P.origin();
+  J.hrows = P.hrows();
   J.inv2nk = P.inv2nk();
   J.weights = P.weights();
   J.slot_kk = P.slot_kk();
@@ -1115,6 +1146,7 @@ PairDesc pair_desc(const Plan& P, const float* ifs, int n_act, int H_in, int W_i
   pd.ifs = ifs;
   pd.out = out;
   pd.origin = P.origin();
+  pd.hrows = P.hrows();
   pd.weights = P.weights();
   pd.slot_kk = P.slot_kk();
   pd.tile_info = P.tile_info();
