@@ -219,17 +219,19 @@ def test_gn_recovers_noise_free(gpu_lib, probe, batched):
     ctx.close()
 
 
-@pytest.mark.parametrize("batched", [False, True], ids=["fused", "batched"])
-def test_gn_matches_oracle_on_noisy_slopes(gpu_lib, probe, batched):
+@pytest.mark.parametrize("batched,n", [(False, 2), (False, 12), (True, 2)],
+                         ids=["fused-multi", "fused-single", "batched"])
+def test_gn_matches_oracle_on_noisy_slopes(gpu_lib, probe, batched, n):
+    """n <= 8 samples split each sample over workgroups; more use one each."""
     import torch
     S = gpu_lib
     pc, wfs, maps = probe
     cfg = pc.scao
-    say(f"[case] GN noisy vs oracle GN batched={batched}")
+    say(f"[case] GN noisy vs oracle GN batched={batched} n={n}")
     F = pc.probe_maps.astype(np.float64)
     scale = 0.5 * (wl.LABEL_HI - wl.LABEL_LO)
     meas, refs = [], []
-    for seed in (1_000_000, 1_000_001):
+    for seed in range(1_000_000, 1_000_000 + n):
         theta, snr, rng = wl.draw_misreg_labels(seed)
         s = omr.probe_slopes(F, theta, cfg.pupil, cfg.p, cfg.valid).ravel()
         s = s + rng.standard_normal(s.size) * (np.sqrt(np.mean(s * s)) / snr)
@@ -237,10 +239,11 @@ def test_gn_matches_oracle_on_noisy_slopes(gpu_lib, probe, batched):
         ref, _, ok = omr.gauss_newton(meas[-1].astype(np.float64), F, cfg.pupil, cfg.p,
                                       cfg.valid, scale, max_iter=30)
         refs.append(ref)
-    ctx = S.Misreg(wfs, maps, wl.LABEL_LO, wl.LABEL_HI, max_batch=2, max_iter=30,
+    ctx = S.Misreg(wfs, maps, wl.LABEL_LO, wl.LABEL_HI, max_batch=n, max_iter=30,
                    gn_batched=batched)
     th, it = ctx.infer(torch.from_numpy(np.stack(meas)).cuda(), S.MISREG_GN)
     th = th.cpu().numpy()
+    assert np.all(it.cpu().numpy() >= 1)   # -1 / -2 would flag a region or sync failure
     refs = np.array(refs)
     say("gpu", th, "oracle", refs)
     assert np.all(np.abs(th[:, :2] - refs[:, :2]) <= 5e-3)
