@@ -746,7 +746,9 @@ const Variant kVariants[] = {
     SYNIM_VARIANT(256, 4, 2, 8, 4, 3),   SYNIM_VARIANT(256, 4, 2, 8, 4, 8),
     SYNIM_VARIANT(1024, 4, 3, 10, 3, 3), SYNIM_VARIANT(512, 4, 3, 10, 3, 6),
     SYNIM_VARIANT(512, 4, 3, 10, 2, 8),  SYNIM_VARIANT(256, 4, 3, 10, 4, 3),
-    SYNIM_VARIANT(256, 4, 3, 10, 4, 8),
+    SYNIM_VARIANT(256, 4, 3, 10, 4, 8),  SYNIM_VARIANT(256, 4, 3, 10, 3, 4),
+    SYNIM_VARIANT(256, 4, 3, 10, 4, 4),  SYNIM_VARIANT(256, 4, 3, 10, 3, 5),
+    SYNIM_VARIANT(256, 4, 3, 10, 3, 3),
     SYNIM_VARIANT(1024, 4, 3, 12, 3, 3), SYNIM_VARIANT(512, 4, 3, 12, 3, 6),
     SYNIM_VARIANT(256, 4, 3, 12, 4, 3),
     SYNIM_VARIANT(512, 8, 2, 12, 3, 6),  SYNIM_VARIANT(256, 8, 2, 12, 6, 3),
@@ -816,8 +818,10 @@ int tiles_for_variant(const synim_wfs& w, const synim_affine& A, const Variant& 
       // (u*p, v*p), so over a tile the origins spread by at most these + 1
       const double sx = std::fabs(A.A[0][0]) * p * (tx - 1) + std::fabs(A.A[0][1]) * p * (ty - 1);
       const double sy = std::fabs(A.A[1][0]) * p * (tx - 1) + std::fabs(A.A[1][1]) * p * (ty - 1);
+      // only the patch rows holding a weight are staged: at most ph_need of
+      // the PH (columns are staged over the full patch width)
       const int BW = ((int)std::floor(sx + 1e-6) + 1 + v.PW + 3 + 3) / 4 * 4;
-      const int BH = (int)std::floor(sy + 1e-6) + 1 + v.PH();
+      const int BH = (int)std::floor(sy + 1e-6) + 1 + ph_need;
       if ((long)BH * BW > v.cap_floats() || BH > MAX_TILE_ROWS) continue;
       const int ux = std::min(tx, w.n_sub_x), uy = std::min(ty, w.n_sub_y);
       const double fill = (double)(ux * uy) / ns;   // lanes with a subaperture
