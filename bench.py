@@ -241,6 +241,9 @@ def main():
     ap.add_argument("--misreg-train", type=int, default=50_000)
     ap.add_argument("--misreg-eval", type=int, default=1000)
     ap.add_argument("--misreg-epochs", type=int, default=60)
+    ap.add_argument("--misreg-replay", action="store_true",
+                    help="only replay the three misregistration estimate modes at batch 1 "
+                         "(the workload of the fit's kernel trace)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -253,6 +256,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_probe_bytes_read": src.numel() * 4,
                           "copy_probe_bytes_written": dst.numel() * 4}), flush=True)
+        return
+    if args.misreg_replay:
+        from paper_2606_07759_amd import learned
+        learned.replay_fits()
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the IM build shards by actuator columns with no "

@@ -403,9 +403,13 @@ int synim_misreg_features(synim_misreg_ctx* c, const float* slopes, int B, const
                           const float* std, float* x, void* stream);
 /* Estimate theta (device float64 [B][4]) from slopes (device [B][n_probe*2N]).
  * mode: SYNIM_MISREG_GN, _MLP, _MLP_GN (GN started from the MLP estimate).
- * iters (device int32 [B], nullable): GN steps taken (0 for MLP).  iter_cap
- * (<= max_iter, 0 = max_iter) bounds the GN loop.  use_graph: replay a graph
- * captured per (B, mode, iter_cap) on `stream` (must not be NULL). */
+ * iters (device int32 [B], nullable): GN steps taken (0 for MLP; -1 / -2 flag
+ * a probe region beyond the context's bound / a lost workgroup sync, neither
+ * expected inside the label box).  iter_cap (<= max_iter, 0 = max_iter)
+ * bounds the GN loop.  use_graph: replay a graph captured on `stream` (must
+ * not be NULL) per (B, mode, iter_cap) and, on the paths that read the
+ * caller's arrays directly (MLP, one-launch Gauss-Newton), per (slopes,
+ * theta, iters) addresses; the 16 most recent graphs are kept. */
 int synim_misreg_infer(synim_misreg_ctx* c, const float* slopes, int B, int mode, double* theta,
                        int32_t* iters, int iter_cap, int use_graph, void* stream);
 /* OR of the plan status words (see synim_plan_status) of the samples of the

@@ -556,13 +556,19 @@ class Misreg:
             _stream_handle(slopes.device)), "misreg_features")
         return x
 
-    def infer(self, slopes, mode=MISREG_GN, iter_cap=0, use_graph=True):
-        """(theta [B][4] float64, iterations [B] int32) on the GPU."""
+    def infer(self, slopes, mode=MISREG_GN, iter_cap=0, use_graph=True, out=None):
+        """(theta [B][4] float64, iterations [B] int32) on the GPU.
+
+        ``out`` = (theta, iterations) tensors to write; reusing them lets the
+        graph captured for these arrays replay with no copies."""
         torch = _torch()
         _dev_f32(slopes, "slopes")
         B = slopes.shape[0]
-        th = torch.empty((B, 4), dtype=torch.float64, device=slopes.device)
-        it = torch.empty(B, dtype=torch.int32, device=slopes.device)
+        if out is not None:
+            th, it = out
+        else:
+            th = torch.empty((B, 4), dtype=torch.float64, device=slopes.device)
+            it = torch.empty(B, dtype=torch.int32, device=slopes.device)
         if use_graph:
             cur = torch.cuda.current_stream(slopes.device)
             self._side.wait_stream(cur)

@@ -190,13 +190,16 @@ def estimator(system: ProbeSystem, trained: Optional[Trained], max_batch: int,
 def time_fit(ctx: Misreg, slopes, mode, reps=20, iter_cap=0):
     """Median and p95 wall time (ms) of one fit call on the GPU (graph replay)."""
     import torch
-    ctx.infer(slopes, mode, iter_cap=iter_cap)            # capture
+    B = slopes.shape[0]
+    out = (torch.empty((B, 4), dtype=torch.float64, device=slopes.device),
+           torch.empty(B, dtype=torch.int32, device=slopes.device))
+    ctx.infer(slopes, mode, iter_cap=iter_cap, out=out)   # capture
     torch.cuda.synchronize()
     ts = []
     for _ in range(reps):
         torch.cuda.synchronize()
         t = time.perf_counter()
-        ctx.infer(slopes, mode, iter_cap=iter_cap)
+        ctx.infer(slopes, mode, iter_cap=iter_cap, out=out)
         torch.cuda.synchronize()
         ts.append((time.perf_counter() - t) * 1e3)
     ts = np.sort(np.array(ts))
@@ -298,6 +301,32 @@ __all__ = ["ProbeSystem", "probe_system", "draw", "synthesize", "net_for", "he_i
            "estimator", "time_fit", "evaluate", "run", "MISREG_GN", "MISREG_MLP", "MISREG_MLP_GN"]
 
 
+def replay_fits(reps: int = 3):
+    """Three graph replays of each estimate mode (GN, MLP, MLP->GN) on one
+    held-out sample, with an untrained (He-initialised) network: the
+    workload a kernel trace of the fit is taken on."""
+    import torch
+    system = probe_system("cuda")
+    theta, snr, noise = draw(np.arange(1_000_000, 1_000_001), system.M)
+    gen = Misreg(system.wfs, system.probes, system.lo, system.hi, max_batch=1)
+    slopes = synthesize(gen, theta, snr, noise, 1)
+    gen.close()
+    net = net_for(system)
+    params = torch.from_numpy(he_init(net, 0)).cuda()
+    mean = torch.zeros(system.M, device="cuda")
+    std = torch.ones(system.M, device="cuda")
+    ctx = Misreg(system.wfs, system.probes, system.lo, system.hi, max_batch=1, max_iter=20,
+                 mlp=(net, params, mean, std, 4000))
+    out = (torch.empty((1, 4), dtype=torch.float64, device="cuda"),
+           torch.empty(1, dtype=torch.int32, device="cuda"))
+    for mode in (MISREG_GN, MISREG_MLP, MISREG_MLP_GN):
+        for _ in range(reps):
+            ctx.infer(slopes, mode, use_graph=True, out=out)
+        torch.cuda.synchronize()
+        print("mode", mode, "iters", out[1].cpu().numpy(), flush=True)
+    ctx.close()
+
+
 if __name__ == "__main__":
     import argparse
     import json
@@ -306,7 +335,12 @@ if __name__ == "__main__":
     ap.add_argument("--n-train", type=int, default=50_000)
     ap.add_argument("--n-eval", type=int, default=1000)
     ap.add_argument("--epochs", type=int, default=60)
+    ap.add_argument("--replay-fits", action="store_true",
+                    help="only replay the three estimate modes (for a kernel trace)")
     args = ap.parse_args()
+    if args.replay_fits:
+        replay_fits()
+        sys.exit(0)
     rep = run(args.n_train, args.n_eval, args.epochs,
               log=lambda m: print(m, file=sys.stderr, flush=True))
     print(json.dumps(rep), flush=True)
