@@ -466,6 +466,10 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
   constexpr int PH = LPS * RPL;
   constexpr int E = PH * PW;
   constexpr int STAGE_F4 = NJ * BLOCK * VW / 4;   // float4 per stage buffer
+  // actuators per stage: at most 4, and few enough that every wait count
+  // (later stages' DMA, stores, sync extras) stays within the vmcnt range
+  constexpr int KPMAX_VM = (63 - (NST - 2) * (NJ + 1) - 1) / (NST - 1);
+  constexpr int KPMAX = KPMAX_VM < 1 ? 1 : (KPMAX_VM > 4 ? 4 : KPMAX_VM);
   static_assert(NST >= 2 && NST <= 8, "2..8 stages");
   static_assert(NJ * (NST - 2) <= 63, "vmcnt range");
   __shared__ int s_item;
@@ -559,128 +563,145 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
       }
     }
 
-    // byte offsets (within one actuator plane) of this lane's DMA vectors;
-    // out-of-range offsets make the buffer unit return zeros
+    // A stage holds KP consecutive actuators' packed tile rows (as many as
+    // fit, up to KPMAX): small tiles then still fill the stage, which keeps
+    // more useful bytes in flight per CU.  The actuators of a chunk are
+    // taken in groups of KP; group gi is actuators a0 + gi*KP .. (< a1).
+    const int cap_f = NJ * BLOCK * VW;
+    const int KP = nfl > 0 ? max(1, min(min(KPMAX, cap_f / nfl), INT_MAX / plane_bytes)) : 1;
+    // byte offsets (within a group's KP consecutive actuator planes) of this
+    // lane's DMA vectors; out-of-range offsets make the buffer unit return
+    // zeros: vectors past the packed rows, outside the IF grid, or (via the
+    // record count) of actuators past the end of the chunk
     unsigned voff[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      const int fo = (BLOCK * j + tid) * VW;   // packed float offset of the vector
+      const int fo = (BLOCK * j + tid) * VW;   // float offset of the vector in the stage
       unsigned v = 0x80000000u;
-      if (fo < nfl) {
-        int lo = 0, hi = ti.y - 1;             // last row whose offset is <= fo
+      const int kp = nfl > 0 ? fo / nfl : KP;
+      if (kp < KP) {
+        const int fr = fo - kp * nfl;          // offset within that actuator's rows
+        int lo = 0, hi = ti.y - 1;             // last row whose offset is <= fr
         while (lo < hi) {
           const int mid = (lo + hi + 1) >> 1;
-          if (rows[mid].y <= fo) lo = mid; else hi = mid - 1;
+          if (rows[mid].y <= fr) lo = mid; else hi = mid - 1;
         }
         const int2 rw = rows[lo];
-        const int gx = rw.x + (fo - rw.y), gy = y0 + lo;
-        if (gx >= 0 && gx + VW <= P.W_in) v = (unsigned)(gy * P.W_in + gx) * 4u;
+        const int gx = rw.x + (fr - rw.y), gy = y0 + lo;
+        if (gx >= 0 && gx + VW <= P.W_in && gy >= 0 && gy < P.H_in)
+          v = (unsigned)kp * (unsigned)plane_bytes + (unsigned)(gy * P.W_in + gx) * 4u;
       }
       voff[j] = v;
     }
     const int a0 = chunk_id * P.chunk;
     const int a1 = min(P.n_act, a0 + P.chunk);
-    // XCD sync (single pair only; E >= NST - 1 is guaranteed by the host)
+    const int n_grp = a1 > a0 ? (a1 - a0 + KP - 1) / KP : 0;
+    // XCD sync (single pair only; E >= NST - 1 groups is guaranteed by the host)
     const bool sync_on = g.pairs == nullptr && g.sync_every > 0;
     const int sync_e = sync_on ? g.sync_every : 1;
     int* sync_ctr = g.sync_ctr + (8 * blockIdx.z + xcd) * SYNC_STRIDE;
     const int n_part = sync_on ? *g.n_active : 0;
     bool sync_live = true;
 
-    auto consume = [&](const float4* buf, int a) {
+    auto consume = [&](const float4* buf, int gi) {
       const float* fb = reinterpret_cast<const float*>(buf);
-      float sx = 0.f, sy = 0.f;
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
+      for (int kp = 0; kp < KPMAX; ++kp) {
+        if (kp >= KP) break;
+        const int a = a0 + gi * KP + kp;
+        const bool act = a < a1;
+        const float* fk = fb + kp * nfl;
+        float sx = 0.f, sy = 0.f;
 #pragma unroll
-        for (int c = 0; c < PW; ++c) {
-          const float f = fb[base[i] + c];
-          sx = __fmaf_rn(wx[i][c], f, sx);
-          sy = __fmaf_rn(wy[i][c], f, sy);
+        for (int i = 0; i < RPL; ++i) {
+#pragma unroll
+          for (int c = 0; c < PW; ++c) {
+            const float f = fk[base[i] + c];
+            sx = __fmaf_rn(wx[i][c], f, sx);
+            sy = __fmaf_rn(wy[i][c], f, sy);
+          }
+        }
+        sx = dpp_sum(sx, LPS);
+        sy = dpp_sum(sy, LPS);
+        const size_t row = (size_t)(act ? a : a0) * 2 * P.nv;
+        if (VJP) {
+          if (act && kk >= 0 && q == 0)
+            vacc += (double)g.grad[row + kk] * sx + (double)g.grad[row + P.nv + kk] * sy;
+        } else {
+          // exactly one store instruction per wave and actuator slot, whatever
+          // the lanes hold: lanes with nothing to write (and the slots past the
+          // chunk's end) target a scratch slot.  The pipeline's wait counts
+          // rely on this number.
+          float* o = P.out + (size_t)(plane - g.out_plane0) * P.n_act * 2 * P.nv + row;
+          const bool real = act && kk >= 0 && q < 2;
+          float* dst = real ? (q == 0 ? o + kk : o + P.nv + kk) : g.scratch + (tid & 63);
+          __builtin_nontemporal_store(q == 0 ? sx : sy, dst);
         }
       }
-      sx = dpp_sum(sx, LPS);
-      sy = dpp_sum(sy, LPS);
-      const size_t row = (size_t)a * 2 * P.nv;
-      if (VJP) {
-        if (kk >= 0 && q == 0)
-          vacc += (double)g.grad[row + kk] * sx + (double)g.grad[row + P.nv + kk] * sy;
-      } else {
-        // exactly one store instruction per wave and actuator, whatever the
-        // lanes hold: lanes with nothing to write target a scratch slot.  The
-        // pipeline's wait counts rely on this number.
-        float* o = P.out + (size_t)(plane - g.out_plane0) * P.n_act * 2 * P.nv + row;
-        const bool real = kk >= 0 && q < 2;
-        float* dst = real ? (q == 0 ? o + kk : o + P.nv + kk) : g.scratch + (tid & 63);
-        __builtin_nontemporal_store(q == 0 ? sx : sy, dst);
-      }
     };
-    // Loads actuator a into stage k.  With the XCD sync on, lane 0 first adds
-    // the workgroup's entry when a opens a block, then snapshots the counter
+    // Loads group gi into stage k.  With the XCD sync on, lane 0 first adds
+    // the workgroup's entry when gi opens a block, then snapshots the counter
     // into s_snap[k]; both precede the stage's DMA.
-    auto issue = [&](int k, float4* buf, int a) {
+    auto issue = [&](int k, float4* buf, int gi) {
       if (sync_on && tid == 0) {
-        if ((a - a0) % sync_e == 0) atomicAdd(sync_ctr, 1);
+        if (gi % sync_e == 0) atomicAdd(sync_ctr, 1);
         snapshot_issue(sync_ctr, s_snap + k);
       }
-      stage_issue<BLOCK, NJ, VW>(P.ifs + (size_t)a * plane_in, plane_bytes, voff, buf, wave);
+      const int a = a0 + gi * KP;
+      const int cnt = min(KP, a1 - a);
+      stage_issue<BLOCK, NJ, VW>(P.ifs + (size_t)a * plane_in, cnt * plane_bytes, voff, buf,
+                                 wave);
     };
-    // one pipeline step for actuator a held in stage K: wait for it (the later
+    // one pipeline step for group gi held in stage K: wait for it (the later
     // stages already issued may stay in flight), make it visible to every
-    // wave, refill the stage freed by the previous step with actuator
-    // a+NST-1, then consume.  Vector-memory operations complete in issue
-    // order, so "at most n in flight", n = the operations issued after this
-    // stage's DMA, means this stage has landed.
-    // The wait counts every vector-memory operation issued after this stage's
-    // DMA: the later stages' DMA (NJ each) and, in the IM kernel, the one store
-    // of each step since then.
+    // wave, refill the stage freed by the previous step with group gi+NST-1,
+    // then consume.  Vector-memory operations complete in issue order, so
+    // "at most n in flight", n = the operations issued after this stage's
+    // DMA, means this stage has landed.  The wait counts every
+    // vector-memory operation issued after this stage's DMA: the later
+    // stages' DMA (NJ each) and, in the IM kernel, the KP stores of each step
+    // since then.
     //
-    // With the XCD sync on, actuator a0 + j with j a multiple of E opens
-    // block j/E, and a workgroup may open block b >= 1 only once every tile
-    // of its XCD has opened block b - 1 (counter >= b * n_part).  Wave 0
-    // checks the snapshot that came with the stage just waited for; only if
-    // that is short does it poll the counter itself (bounded: a workgroup
-    // that waits too long stops waiting but keeps adding its entries, so the
-    // counts stay exact).  Wave 0 also issues, per loaded actuator, the
-    // snapshot and possibly an entry atomic; its wait counts them.
-    auto step = [&](auto kc, int a) {
+    // With the XCD sync on, group j with j a multiple of E opens block j/E,
+    // and a workgroup may open block b >= 1 only once every tile of its XCD
+    // has opened block b - 1 (counter >= b * n_part).  Wave 0 checks the
+    // snapshot that came with the stage just waited for; only if that is
+    // short does it poll the counter itself (bounded: a workgroup that waits
+    // too long stops waiting but keeps adding its entries, so the counts stay
+    // exact).  Wave 0 also issues, per loaded group, the snapshot and
+    // possibly an entry atomic; its wait counts them.
+    auto step = [&](auto kc, int gi) {
       constexpr int K = decltype(kc)::value;
-      const int later = min(NST - 2, a1 - 1 - a);
-      const int stores = VJP ? 0 : min(a - a0, NST - 1);
-      const int x = a + NST - 1;   // the actuator this step starts loading
+      const int later = min(NST - 2, n_grp - 1 - gi);
+      const int stores = VJP ? 0 : KP * min(gi, NST - 1);
+      const int x = gi + NST - 1;   // the group this step starts loading
       int extra = 0;
-      if (sync_on && wave == 0) {
-        const int j = a - a0;
-        extra = later + (j + later) / sync_e - j / sync_e;
-      }
+      if (sync_on && wave == 0) extra = later + (gi + later) / sync_e - gi / sync_e;
       wait_vm(later * NJ + stores + extra);
-      if (sync_on && wave == 0 && sync_live && x < a1) {
-        const int jx = x - a0;
-        if (jx > 0 && jx % sync_e == 0) {
-          const int target = (jx / sync_e) * n_part;
-          if (s_snap[K] < target) {
-            int it = 0;
-            while (__hip_atomic_load(sync_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-                   target) {
-              if (++it >= SYNC_SPIN_MAX) {
-                sync_live = false;
-                break;
-              }
-              __builtin_amdgcn_s_sleep(4);
+      if (sync_on && wave == 0 && sync_live && x < n_grp && x > 0 && x % sync_e == 0) {
+        const int target = (x / sync_e) * n_part;
+        if (s_snap[K] < target) {
+          int it = 0;
+          while (__hip_atomic_load(sync_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+                 target) {
+            if (++it >= SYNC_SPIN_MAX) {
+              sync_live = false;
+              break;
             }
+            __builtin_amdgcn_s_sleep(4);
           }
         }
       }
       __builtin_amdgcn_s_barrier();
-      if (x < a1) issue((K + NST - 1) % NST, stage_buf<(K + NST - 1) % NST, STAGE_F4>(), x);
-      consume(stage_buf<K, STAGE_F4>(), a);
+      if (x < n_grp) issue((K + NST - 1) % NST, stage_buf<(K + NST - 1) % NST, STAGE_F4>(), x);
+      consume(stage_buf<K, STAGE_F4>(), gi);
     };
     [&]<int... K>(std::integer_sequence<int, K...>) {
-      ((a0 + K < a1 && K < NST - 1 ? issue(K, stage_buf<K, STAGE_F4>(), a0 + K) : void()), ...);
+      ((K < n_grp && K < NST - 1 ? issue(K, stage_buf<K, STAGE_F4>(), K) : void()), ...);
     }(std::make_integer_sequence<int, NST>{});
-    for (int a = a0; a < a1; a += NST) {
+    for (int gb = 0; gb < n_grp; gb += NST) {
       [&]<int... K>(std::integer_sequence<int, K...>) {
-        ((a + K < a1 ? step(std::integral_constant<int, K>{}, a + K) : void()), ...);
+        ((gb + K < n_grp ? step(std::integral_constant<int, K>{}, gb + K) : void()), ...);
       }(std::make_integer_sequence<int, NST>{});
     }
   }
@@ -748,7 +769,7 @@ const Variant kVariants[] = {
     SYNIM_VARIANT(512, 4, 3, 10, 2, 8),  SYNIM_VARIANT(256, 4, 3, 10, 4, 3),
     SYNIM_VARIANT(256, 4, 3, 10, 4, 8),  SYNIM_VARIANT(256, 4, 3, 10, 3, 4),
     SYNIM_VARIANT(256, 4, 3, 10, 4, 4),  SYNIM_VARIANT(256, 4, 3, 10, 3, 5),
-    SYNIM_VARIANT(256, 4, 3, 10, 3, 3),
+    SYNIM_VARIANT(256, 4, 3, 10, 3, 3),  SYNIM_VARIANT(256, 4, 3, 10, 6, 3),
     SYNIM_VARIANT(1024, 4, 3, 12, 3, 3), SYNIM_VARIANT(512, 4, 3, 12, 3, 6),
     SYNIM_VARIANT(256, 4, 3, 12, 4, 3),
     SYNIM_VARIANT(512, 8, 2, 12, 3, 6),  SYNIM_VARIANT(256, 8, 2, 12, 6, 3),
