@@ -214,25 +214,30 @@ int synim_im_autotune(const float* ifs, int n_act, int H_in, int W_in, const syn
                       const synim_wfs* wfs, float* im, void* ws, size_t ws_bytes,
                       int max_candidates, float* times_ms, int* n_tried, void* stream);
 
-/* The configuration plan/apply would use now: out8 (host) = block size,
- * lanes per subaperture, patch rows, patch columns, tile width and height in
- * subapertures, pipeline stages, schedule: 0 = short actuator chunks dealt
- * round-robin to the XCDs; 1 = one chunk per XCD with every tile of it
- * running at once, one tile per workgroup; E >= 2 = as 1, with the tiles of
- * an XCD kept within one block of E actuators of each other. */
-int synim_im_config(const synim_wfs* wfs, const synim_affine* A, int* out8);
+/* Ints in one kernel configuration record. */
+#define SYNIM_CONFIG_INTS 10
+
+/* The configuration plan/apply would use now: out (host,
+ * [SYNIM_CONFIG_INTS]) = block size, lanes per subaperture, patch rows,
+ * patch columns, tile width and height in subapertures, pipeline stages,
+ * schedule, 16-byte DMA instructions per wave and stage, most actuators one
+ * stage holds.  Schedule: 0 = short actuator chunks dealt round-robin to the
+ * XCDs; 1 = one chunk per XCD with every tile of it running at once, one
+ * tile per workgroup; E >= 2 = as 1, with the tiles of an XCD kept within
+ * one block of E actuators of each other. */
+int synim_im_config(const synim_wfs* wfs, const synim_affine* A, int* out);
 
 /* The candidate configurations synim_im_autotune tries, in its order (cost
- * model first): out8 (host, [max_out][8]) as synim_im_config; *n_out (host)
- * receives the count written. */
-int synim_im_candidates(const synim_wfs* wfs, const synim_affine* A, int* out8, int max_out,
+ * model first): out (host, [max_out][SYNIM_CONFIG_INTS]) as
+ * synim_im_config; *n_out (host) receives the count written (at most 256). */
+int synim_im_candidates(const synim_wfs* wfs, const synim_affine* A, int* out, int max_out,
                         int* n_out);
 
 /* Pin the configuration later plan/apply/build calls use for this geometry
- * (as if the autotuner had picked it): config8 (host) as synim_im_config,
- * one of synim_im_candidates.  Errors: SYNIM_E_NULL, SYNIM_E_SHAPE,
- * SYNIM_E_UNSUPPORTED (not a candidate for this geometry). */
-int synim_im_set_config(const synim_wfs* wfs, const synim_affine* A, const int* config8);
+ * (as if the autotuner had picked it): config (host, [SYNIM_CONFIG_INTS]) as
+ * synim_im_config, one of synim_im_candidates.  Errors: SYNIM_E_NULL,
+ * SYNIM_E_SHAPE, SYNIM_E_UNSUPPORTED (not a candidate for this geometry). */
+int synim_im_set_config(const synim_wfs* wfs, const synim_affine* A, const int* config);
 
 /* Forget every autotuned configuration. */
 void synim_autotune_clear(void);
@@ -302,8 +307,10 @@ int synim_batch_status(synim_batch* b, int* host_out, void* stream);
 int synim_batch_autotune(synim_batch* b, int max_variants, float* times_ms, int* n_tried,
                          void* stream);
 
-/* out4 (host) = block size, lanes per subaperture, pipeline stages, grid. */
-int synim_batch_config(const synim_batch* b, int* out4);
+/* out6 (host) = block size, lanes per subaperture, pipeline stages, grid,
+ * 16-byte DMA instructions per wave and stage, most actuators one stage
+ * holds. */
+int synim_batch_config(const synim_batch* b, int* out6);
 
 /* Release the handle (the workspace stays the caller's). */
 void synim_batch_destroy(synim_batch* b);

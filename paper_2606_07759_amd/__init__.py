@@ -291,35 +291,36 @@ def im_autotune(ifs, A, wfs: Wfs, max_candidates: int = 8, ws=None):
 
 
 _CFG_KEYS = ("block", "lanes_per_subap", "patch_rows", "patch_cols", "tile_x", "tile_y", "stages",
-             "schedule")
+             "schedule", "dma_per_wave", "pack")
+_NCFG = len(_CFG_KEYS)
 
 
 def im_config(wfs: Wfs, A) -> dict:
     """Kernel configuration plan/apply would use for this geometry now."""
     lib = load()
-    o = (C.c_int * 8)()
+    o = (C.c_int * _NCFG)()
     s = wfs.struct()
     a = _affine_struct(A)
     _check(lib.synim_im_config(C.byref(s), C.byref(a), o), "im_config")
-    return dict(zip(_CFG_KEYS, o[:8]))
+    return dict(zip(_CFG_KEYS, o[:_NCFG]))
 
 
-def im_candidates(wfs: Wfs, A, max_out: int = 160) -> list:
+def im_candidates(wfs: Wfs, A, max_out: int = 256) -> list:
     """Candidate kernel configurations in the autotuner's order."""
     lib = load()
-    o = (C.c_int * (8 * max_out))()
+    o = (C.c_int * (_NCFG * max_out))()
     n = C.c_int(0)
     s = wfs.struct()
     a = _affine_struct(A)
     _check(lib.synim_im_candidates(C.byref(s), C.byref(a), o, max_out, C.byref(n)),
            "im_candidates")
-    return [dict(zip(_CFG_KEYS, o[8 * i:8 * i + 8])) for i in range(n.value)]
+    return [dict(zip(_CFG_KEYS, o[_NCFG * i:_NCFG * (i + 1)])) for i in range(n.value)]
 
 
 def im_set_config(wfs: Wfs, A, config: dict):
     """Pin one of :func:`im_candidates` for this geometry."""
     lib = load()
-    o = (C.c_int * 8)(*[int(config[k]) for k in _CFG_KEYS])
+    o = (C.c_int * _NCFG)(*[int(config[k]) for k in _CFG_KEYS])
     s = wfs.struct()
     a = _affine_struct(A)
     _check(lib.synim_im_set_config(C.byref(s), C.byref(a), o), "im_set_config")
@@ -414,9 +415,10 @@ class Batch:
         return [float(t[i]) for i in range(n.value)]
 
     def config(self) -> dict:
-        o = (C.c_int * 4)()
+        o = (C.c_int * 6)()
         _check(load().synim_batch_config(self._h, o), "batch_config")
-        return dict(block=o[0], lanes_per_subap=o[1], stages=o[2], grid=o[3])
+        return dict(block=o[0], lanes_per_subap=o[1], stages=o[2], grid=o[3],
+                    dma_per_wave=o[4], pack=o[5])
 
     def close(self):
         if self._h and self._h.value:

@@ -455,21 +455,26 @@ __device__ __forceinline__ void snapshot_issue(const int* ctr, int* lds_dst) {
   __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)lds_dst, 4, 0, 0, 0, SNAP_AUX);
 }
 
+// Actuators one stage may hold: PACK (1 = one actuator per stage), cut to
+// what keeps every wait count of the pipeline (the later stages' DMA, the
+// stores of the steps since, the sync extras) within the vmcnt range.
+constexpr int stage_pack(int nj, int nst, int pack) {
+  const int vm = (63 - (nst - 2) * (nj + 1) - 1) / (nst - 1);
+  return pack <= 1 || vm < 1 ? 1 : (vm < pack ? vm : pack);
+}
+
 // Persistent streaming kernel.  Work items are (actuator chunk, tile) pairs;
 // workgroup b serves the queue of its XCD (b mod 8 - consecutive workgroups are
 // dispatched round-robin over the 8 XCDs), and each queue walks its chunks in
 // order, tiles fastest, so the tiles of one chunk run side by side on one XCD
 // and share the IF rows of their halos in that XCD's L2.  Within an item the
 // actuators stream through NST LDS stages with NST-1 actuators in flight.
-template <int BLOCK, int LPS, int RPL, int PW, int NJ, int VW, int NST, bool VJP>
+template <int BLOCK, int LPS, int RPL, int PW, int NJ, int VW, int NST, int PACK, bool VJP>
 __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
   constexpr int PH = LPS * RPL;
   constexpr int E = PH * PW;
   constexpr int STAGE_F4 = NJ * BLOCK * VW / 4;   // float4 per stage buffer
-  // actuators per stage: at most 4, and few enough that every wait count
-  // (later stages' DMA, stores, sync extras) stays within the vmcnt range
-  constexpr int KPMAX_VM = (63 - (NST - 2) * (NJ + 1) - 1) / (NST - 1);
-  constexpr int KPMAX = KPMAX_VM < 1 ? 1 : (KPMAX_VM > 4 ? 4 : KPMAX_VM);
+  constexpr int KPMAX = stage_pack(NJ, NST, PACK);
   static_assert(NST >= 2 && NST <= 8, "2..8 stages");
   static_assert(NJ * (NST - 2) <= 63, "vmcnt range");
   __shared__ int s_item;
@@ -568,7 +573,9 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
     // more useful bytes in flight per CU.  The actuators of a chunk are
     // taken in groups of KP; group gi is actuators a0 + gi*KP .. (< a1).
     const int cap_f = NJ * BLOCK * VW;
-    const int KP = nfl > 0 ? max(1, min(min(KPMAX, cap_f / nfl), INT_MAX / plane_bytes)) : 1;
+    const int KP = KPMAX == 1 || nfl == 0
+                       ? 1
+                       : max(1, min(min(KPMAX, cap_f / nfl), INT_MAX / plane_bytes));
     // byte offsets (within a group's KP consecutive actuator planes) of this
     // lane's DMA vectors; out-of-range offsets make the buffer unit return
     // zeros: vectors past the packed rows, outside the IF grid, or (via the
@@ -578,7 +585,7 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
     for (int j = 0; j < NJ; ++j) {
       const int fo = (BLOCK * j + tid) * VW;   // float offset of the vector in the stage
       unsigned v = 0x80000000u;
-      const int kp = nfl > 0 ? fo / nfl : KP;
+      const int kp = KPMAX == 1 ? (fo < nfl ? 0 : 1) : (nfl > 0 ? fo / nfl : KP);
       if (kp < KP) {
         const int fr = fo - kp * nfl;          // offset within that actuator's rows
         int lo = 0, hi = ti.y - 1;             // last row whose offset is <= fr
@@ -741,6 +748,7 @@ using StreamFn = void (*)(StreamArgs);
 
 struct Variant {
   int BLOCK, LPS, RPL, PW, NJ4, NST;   // NJ4: 16-byte DMA instructions per wave per stage
+  int PACK;                            // most actuators one stage holds
   StreamFn im4, vjp4;                  // 16-byte DMA: rows a multiple of 4 floats, aligned stack
   StreamFn im1, vjp1;                  // 4-byte DMA: any row length / alignment
   int PH() const { return LPS * RPL; }
@@ -751,15 +759,20 @@ struct Variant {
 // vmcnt counter can express
 constexpr int nst_vw1(int n, int s) { return s < 2 + 63 / (4 * n) ? s : 2 + 63 / (4 * n); }
 
-#define SYNIM_VARIANT(B, L, R, W, N, S)                                                \
-  {B, L, R, W, N, S, im_stream_kernel<B, L, R, W, N, 4, S, false>,                     \
-   im_stream_kernel<B, L, R, W, N, 4, S, true>,                                        \
-   im_stream_kernel<B, L, R, W, 4 * N, 1, nst_vw1(N, S), false>,                       \
-   im_stream_kernel<B, L, R, W, 4 * N, 1, nst_vw1(N, S), true>}
+#define SYNIM_VARIANT_K(B, L, R, W, N, S, K)                                           \
+  {B, L, R, W, N, S, stage_pack(N, S, K), im_stream_kernel<B, L, R, W, N, 4, S, K, false>, \
+   im_stream_kernel<B, L, R, W, N, 4, S, K, true>,                                     \
+   im_stream_kernel<B, L, R, W, 4 * N, 1, nst_vw1(N, S), K, false>,                    \
+   im_stream_kernel<B, L, R, W, 4 * N, 1, nst_vw1(N, S), K, true>}
+#define SYNIM_VARIANT(B, L, R, W, N, S) SYNIM_VARIANT_K(B, L, R, W, N, S, 1)
+#define SYNIM_VARIANT_PACK(B, L, R, W, N, S) SYNIM_VARIANT_K(B, L, R, W, N, S, 4)
 
 // (block, lanes/subaperture, rows/lane, patch columns, DMA per wave per stage,
 // stages).  Three stages of small tiles let several workgroups share a CU;
-// deeper pipelines of one workgroup per CU keep more bytes in flight.
+// deeper pipelines of one workgroup per CU keep more bytes in flight.  The
+// _PACK twins put up to 4 actuators in a stage when a tile's rows fill half
+// of it or less (steep or small tiles), so such stages still carry full
+// loads.
 const Variant kVariants[] = {
     SYNIM_VARIANT(1024, 4, 2, 8, 3, 3),  SYNIM_VARIANT(512, 4, 2, 8, 3, 6),
     SYNIM_VARIANT(512, 4, 2, 8, 3, 3),   SYNIM_VARIANT(512, 4, 3, 10, 3, 3),
@@ -778,6 +791,11 @@ const Variant kVariants[] = {
     SYNIM_VARIANT(512, 8, 2, 14, 3, 6),  SYNIM_VARIANT(256, 8, 2, 14, 6, 3),
     SYNIM_VARIANT(512, 8, 2, 16, 3, 6),  SYNIM_VARIANT(256, 8, 2, 16, 6, 3),
     SYNIM_VARIANT(256, 8, 3, 20, 6, 3),  SYNIM_VARIANT(256, 8, 3, 24, 6, 3),
+    SYNIM_VARIANT_PACK(256, 4, 2, 8, 4, 3),   SYNIM_VARIANT_PACK(256, 4, 3, 10, 4, 3),
+    SYNIM_VARIANT_PACK(256, 4, 3, 10, 6, 3),  SYNIM_VARIANT_PACK(256, 4, 3, 12, 4, 3),
+    SYNIM_VARIANT_PACK(256, 8, 2, 12, 6, 3),  SYNIM_VARIANT_PACK(256, 8, 2, 14, 6, 3),
+    SYNIM_VARIANT_PACK(256, 8, 2, 16, 6, 3),  SYNIM_VARIANT_PACK(256, 8, 3, 20, 6, 3),
+    SYNIM_VARIANT_PACK(256, 8, 3, 24, 6, 3),
 };
 constexpr int kNumVariants = sizeof(kVariants) / sizeof(kVariants[0]);
 
@@ -849,6 +867,10 @@ int tiles_for_variant(const synim_wfs& w, const synim_affine& A, const Variant& 
       const long tiles = (long)((w.n_sub_x + tx - 1) / tx) * ((w.n_sub_y + ty - 1) / ty);
       double cost = (double)(BW + 24) * BH / ((double)ux * uy) / fill;
       if (tiles * 8 < 64 && n_sub > 64) cost *= 1.5;   // too few tiles to spread
+      // a packing twin ranks ahead of its one-actuator variant where the
+      // tile bound leaves room for two actuators per stage, behind it
+      // elsewhere (the exact rows may still leave room)
+      if (v.PACK > 1) cost *= 2L * BH * BW <= v.cap_floats() ? 0.95 : 1.02;
       Dims d{};
       d.var = &v;
       d.PH = v.PH();
@@ -930,7 +952,21 @@ int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double*
   return n;
 }
 
-constexpr int MAX_CAND = 160;
+constexpr int MAX_CAND = 256;
+
+// The configuration record of synim_im_config / synim_im_candidates.
+void write_config(const Dims& d, int* o) {
+  o[0] = d.var->BLOCK;
+  o[1] = d.var->LPS;
+  o[2] = d.PH;
+  o[3] = d.PW;
+  o[4] = d.TX;
+  o[5] = d.TY;
+  o[6] = d.var->NST;
+  o[7] = d.sched == SCHED_XCD ? (d.sync_every > 0 ? d.sync_every : 1) : 0;
+  o[8] = d.var->NJ4;
+  o[9] = d.var->PACK;
+}
 
 // Autotune cache: geometry key -> (variant, tile shape) measured fastest.
 struct TuneKey {
@@ -1312,50 +1348,33 @@ extern "C" int synim_im_autotune(const float* ifs, int n_act, int H_in, int W_in
   return SYNIM_OK;
 }
 
-extern "C" int synim_im_config(const synim_wfs* wfs, const synim_affine* A, int* out8) {
-  if (!wfs || !A || !out8) return SYNIM_E_NULL;
+extern "C" int synim_im_config(const synim_wfs* wfs, const synim_affine* A, int* out) {
+  if (!wfs || !A || !out) return SYNIM_E_NULL;
   int rc = validate_wfs(wfs);
   if (rc != SYNIM_OK) return rc;
   Dims d{};
   rc = choose_dims(*wfs, *A, &d);
   if (rc != SYNIM_OK) return rc;
-  out8[0] = d.var->BLOCK;
-  out8[1] = d.var->LPS;
-  out8[2] = d.PH;
-  out8[3] = d.PW;
-  out8[4] = d.TX;
-  out8[5] = d.TY;
-  out8[6] = d.var->NST;
-  out8[7] = d.sched == SCHED_XCD ? (d.sync_every > 0 ? d.sync_every : 1) : 0;
+  write_config(d, out);
   return SYNIM_OK;
 }
 
-extern "C" int synim_im_candidates(const synim_wfs* wfs, const synim_affine* A, int* out8,
+extern "C" int synim_im_candidates(const synim_wfs* wfs, const synim_affine* A, int* out,
                                    int max_out, int* n_out) {
-  if (!wfs || !A || !out8 || !n_out) return SYNIM_E_NULL;
+  if (!wfs || !A || !out || !n_out) return SYNIM_E_NULL;
   int rc = validate_wfs(wfs);
   if (rc != SYNIM_OK) return rc;
   Dims cand[MAX_CAND];
   double cost[MAX_CAND];
   const int n = std::min(max_out, candidate_dims(*wfs, *A, cand, cost, MAX_CAND));
-  for (int i = 0; i < n; ++i) {
-    int* o = out8 + 8 * i;
-    o[0] = cand[i].var->BLOCK;
-    o[1] = cand[i].var->LPS;
-    o[2] = cand[i].PH;
-    o[3] = cand[i].PW;
-    o[4] = cand[i].TX;
-    o[5] = cand[i].TY;
-    o[6] = cand[i].var->NST;
-    o[7] = cand[i].sched == SCHED_XCD ? (cand[i].sync_every > 0 ? cand[i].sync_every : 1) : 0;
-  }
+  for (int i = 0; i < n; ++i) write_config(cand[i], out + SYNIM_CONFIG_INTS * i);
   *n_out = n;
   return SYNIM_OK;
 }
 
 extern "C" int synim_im_set_config(const synim_wfs* wfs, const synim_affine* A,
-                                   const int* config8) {
-  if (!wfs || !A || !config8) return SYNIM_E_NULL;
+                                   const int* config) {
+  if (!wfs || !A || !config) return SYNIM_E_NULL;
   int rc = validate_wfs(wfs);
   if (rc != SYNIM_OK) return rc;
   Dims cand[MAX_CAND];
@@ -1363,11 +1382,9 @@ extern "C" int synim_im_set_config(const synim_wfs* wfs, const synim_affine* A,
   const int n = candidate_dims(*wfs, *A, cand, cost, MAX_CAND);
   for (int c = 0; c < n; ++c) {
     const Dims& d = cand[c];
-    const int sched = d.sched == SCHED_XCD ? (d.sync_every > 0 ? d.sync_every : 1) : 0;
-    if (d.var->BLOCK != config8[0] || d.var->LPS != config8[1] || d.PH != config8[2] ||
-        d.PW != config8[3] || d.TX != config8[4] || d.TY != config8[5] ||
-        d.var->NST != config8[6] || sched != config8[7])
-      continue;
+    int mine[SYNIM_CONFIG_INTS];
+    write_config(d, mine);
+    if (!std::equal(mine, mine + SYNIM_CONFIG_INTS, config)) continue;
     const TuneKey key = tune_key(*wfs, *A);
     TuneEntry e{key, (int)(d.var - kVariants), d.TX, d.TY, d.NSLOT, d.sched, d.sync_every};
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -1927,12 +1944,14 @@ extern "C" int synim_batch_autotune(synim_batch* b, int max_variants, float* tim
   return batch_bind(b, *batch_variant(b, best), st);
 }
 
-extern "C" int synim_batch_config(const synim_batch* b, int* out4) {
-  if (!b || !out4 || !b->var) return SYNIM_E_NULL;
-  out4[0] = b->var->BLOCK;
-  out4[1] = b->var->LPS;
-  out4[2] = b->var->NST;
-  out4[3] = b->G;
+extern "C" int synim_batch_config(const synim_batch* b, int* out6) {
+  if (!b || !out6 || !b->var) return SYNIM_E_NULL;
+  out6[0] = b->var->BLOCK;
+  out6[1] = b->var->LPS;
+  out6[2] = b->var->NST;
+  out6[3] = b->G;
+  out6[4] = b->var->NJ4;
+  out6[5] = b->var->PACK;
   return SYNIM_OK;
 }
 
