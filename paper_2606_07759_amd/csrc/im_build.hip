@@ -389,25 +389,54 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 // s_waitcnt immediates (gfx9 encoding) that wait on vmcnt only.
 constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14); }
 
-// Streams one actuator's packed tile rows into an LDS stage buffer with
-// buffer->LDS DMA.  Each wave issues exactly NJ instructions per stage, so the
-// number of vector-memory operations in flight is known at compile time.  The
-// buffer resource covers the actuator's IF plane only: rows above/below the
-// grid fall outside its range and read as zero; columns outside the grid are
-// sent out of range explicitly.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Raw buffer resource (stride 0, range-checked) over [base, base + bytes),
+// every word wave-uniform so it lives in SGPRs.
+__device__ __forceinline__ u32x4 buffer_rsrc(const void* base, unsigned bytes) {
+  const unsigned long long a = reinterpret_cast<unsigned long long>(base);
+  u32x4 r;
+  r.x = __builtin_amdgcn_readfirstlane((unsigned)a);
+  r.y = __builtin_amdgcn_readfirstlane((unsigned)(a >> 32));   // stride 0
+  r.z = __builtin_amdgcn_readfirstlane(bytes);
+  r.w = 0x00020000u;
+  return r;
+}
+
+// LDS byte address of a __shared__ location, wave-uniform (M0 operand).
+__device__ __forceinline__ unsigned lds_addr(const void* p) {
+  return __builtin_amdgcn_readfirstlane(
+      (unsigned)(size_t)(lds_void_t*)const_cast<void*>(p));
+}
+
+// Compiler-only ordering point: no memory access moves across it.
+__device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory"); }
+
+// Streams one group of actuators' packed tile rows into an LDS stage buffer
+// with buffer->LDS DMA.  Each wave issues exactly NJ instructions per stage,
+// so the number of vector-memory operations in flight is known at compile
+// time.  The buffer resource covers the group's IF planes only: rows
+// above/below the grid fall outside its range and read as zero; columns
+// outside the grid are sent out of range explicitly.
+//
+// The DMA is written as inline assembly on purpose: the compiler then tracks
+// no LDS write for it and adds no wait of its own before the stage reads
+// (its conservative merge at the pipeline loop head drained every DMA in
+// flight there).  Completion is the pipeline's explicit vmcnt waits alone.
 template <int BLOCK, int NJ, int VW>
 __device__ __forceinline__ void stage_issue(const float* plane_ptr, int plane_bytes,
                                             const unsigned* voff, float4* buf, int wave) {
-  __amdgpu_buffer_rsrc_t r =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<float*>(plane_ptr), (short)0, plane_bytes,
-                                        0x00020000);
+  const u32x4 r = buffer_rsrc(plane_ptr, (unsigned)plane_bytes);
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
-    float* dst = reinterpret_cast<float*>(buf) + (size_t)(BLOCK * j + 64 * wave) * VW;
+    const unsigned m0 =
+        lds_addr(reinterpret_cast<float*>(buf) + (size_t)(BLOCK * j + 64 * wave) * VW);
     if constexpr (VW == 4)
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)dst, 16, voff[j], 0, 0, 0);
+      asm volatile("buffer_load_dwordx4 %0, %1, 0 offen lds" ::"v"(voff[j]), "s"(r), "{m0}"(m0)
+                   : "memory");
     else
-      __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)dst, 4, voff[j], 0, 0, 0);
+      asm volatile("buffer_load_dword %0, %1, 0 offen lds" ::"v"(voff[j]), "s"(r), "{m0}"(m0)
+                   : "memory");
   }
 }
 
@@ -434,6 +463,15 @@ __device__ __forceinline__ void wait_vm(int n) {
 #undef SYNIM_W
     default: __builtin_amdgcn_s_waitcnt(waitcnt_vm(0)); break;
   }
+  compiler_fence();
+}
+
+// s_barrier with compiler ordering points on both sides: the stage reads of
+// the step before stay above it, the reads of the next stage below it.
+__device__ __forceinline__ void stage_barrier() {
+  compiler_fence();
+  __builtin_amdgcn_s_barrier();
+  compiler_fence();
 }
 
 // XCD sync bookkeeping.  The block-entry counter of a workgroup's XCD is read
@@ -445,14 +483,14 @@ __device__ __forceinline__ void wait_vm(int n) {
 //    sees the other workgroups' atomics;
 //  * a device-scope atomic load, only when a snapshot says the peers are
 //    behind (the wave then waits for it, draining its own DMA queue).
-constexpr int SNAP_AUX = 16;          // sc1: device scope
 constexpr int SYNC_SPIN_MAX = 1000;   // polls before a workgroup stops syncing
 constexpr int SYNC_STRIDE = 32;       // ints between the counters (own 128-byte line)
 
 __device__ __forceinline__ void snapshot_issue(const int* ctr, int* lds_dst) {
-  __amdgpu_buffer_rsrc_t r =
-      __builtin_amdgcn_make_buffer_rsrc(const_cast<int*>(ctr), (short)0, 4, 0x00020000);
-  __builtin_amdgcn_raw_ptr_buffer_load_lds(r, (lds_void_t*)lds_dst, 4, 0, 0, 0, SNAP_AUX);
+  const u32x4 r = buffer_rsrc(ctr, 4u);
+  const unsigned m0 = lds_addr(lds_dst);
+  asm volatile("buffer_load_dword %0, %1, 0 offen sc1 lds" ::"v"(0u), "s"(r), "{m0}"(m0)
+               : "memory");
 }
 
 // Actuators one stage may hold: PACK (1 = one actuator per stage), cut to
@@ -495,6 +533,9 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
   }
   int* ctr = g.counters + 8 * blockIdx.z + xcd;
   double vacc = 0.0;
+  // read once, before any DMA: a compiler-tracked load still pending at the
+  // pipeline loop head would make the compiler drain the DMA queue there
+  const int n_part = g.pairs == nullptr && g.sync_every > 0 ? *g.n_active : 0;
 
   for (;;) {
     __syncthreads();   // the previous item's stage buffers are free again
@@ -607,7 +648,6 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
     const bool sync_on = g.pairs == nullptr && g.sync_every > 0;
     const int sync_e = sync_on ? g.sync_every : 1;
     int* sync_ctr = g.sync_ctr + (8 * blockIdx.z + xcd) * SYNC_STRIDE;
-    const int n_part = sync_on ? *g.n_active : 0;
     bool sync_live = true;
 
     auto consume = [&](const float4* buf, int gi) {
@@ -699,10 +739,16 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
           }
         }
       }
-      __builtin_amdgcn_s_barrier();
+      stage_barrier();
       if (x < n_grp) issue((K + NST - 1) % NST, stage_buf<(K + NST - 1) % NST, STAGE_F4>(), x);
       consume(stage_buf<K, STAGE_F4>(), gi);
     };
+    // every compiler-tracked load of the item (weights, rows) has landed
+    // before the first DMA; otherwise the compiler would wait for them at
+    // their first use inside the pipeline, with vmcnt(0), draining the DMA
+    // queue at every loop head.  The row search above already waited on
+    // loads issued after the weights, so this costs next to nothing.
+    wait_vm(0);
     [&]<int... K>(std::integer_sequence<int, K...>) {
       ((K < n_grp && K < NST - 1 ? issue(K, stage_buf<K, STAGE_F4>(), K) : void()), ...);
     }(std::make_integer_sequence<int, NST>{});
