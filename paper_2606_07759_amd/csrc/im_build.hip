@@ -507,8 +507,22 @@ constexpr int stage_pack(int nj, int nst, int pack) {
 // order, tiles fastest, so the tiles of one chunk run side by side on one XCD
 // and share the IF rows of their halos in that XCD's L2.  Within an item the
 // actuators stream through NST LDS stages with NST-1 actuators in flight.
+// Waves per SIMD the stream kernel runs at when LDS is what limits its
+// workgroups per CU (160 KB per CU, at most 8 waves per SIMD): the register
+// budget of the 16-byte DMA variants is set to match, so registers never cut
+// that occupancy further.  (The 4-byte DMA variants hold four times the DMA
+// offsets and keep the compiler's own budget.)
+constexpr int stream_waves_per_simd(int block, int nj, int vw, int nst) {
+  const int lds = nst * nj * block * vw * 4 + MAX_TILE_ROWS * 8 + 1024;
+  int wgs = 160 * 1024 / lds;
+  if (wgs * block > 2048) wgs = 2048 / block;
+  const int w = wgs * (block / 64) / 4;
+  return w < 1 ? 1 : (w > 8 ? 8 : w);
+}
+
 template <int BLOCK, int LPS, int RPL, int PW, int NJ, int VW, int NST, int PACK, bool VJP>
-__global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
+__global__ __launch_bounds__(BLOCK, VW == 4 ? stream_waves_per_simd(BLOCK, NJ, VW, NST) : 1) void
+im_stream_kernel(StreamArgs g) {
   constexpr int PH = LPS * RPL;
   constexpr int E = PH * PW;
   constexpr int STAGE_F4 = NJ * BLOCK * VW / 4;   // float4 per stage buffer
@@ -518,42 +532,55 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
   __shared__ int s_item;
   __shared__ double s_red[BLOCK / 64];
   __shared__ int s_snap[NST];   // per stage: block-entry counter when it was issued
+  __shared__ int2 s_rows[MAX_TILE_ROWS];   // the current tile's row table
 
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int slot = tid / LPS, q = tid % LPS;
   const int xcd = blockIdx.x & 7;
   const int plane = g.plane0 + blockIdx.z;
-  int n_items;
-  if (g.pairs == nullptr) {
-    const int nc_x = g.one.n_chunks > xcd ? (g.one.n_chunks - xcd + 7) / 8 : 0;
-    n_items = nc_x * g.one.n_tiles;
-  } else {
-    n_items = g.xcd_items[xcd];
-  }
-  int* ctr = g.counters + 8 * blockIdx.z + xcd;
+  // Items of XCD queue x.  A workgroup starts on its own XCD's queue and,
+  // once that is empty, takes what is left in the other queues (in order
+  // x+1, x+2, ...), so no XCD idles while another still has items.  With
+  // the bounded-lag sync on, the workgroups of an XCD must stay on its queue.
+  auto queue_items = [&](int x) {
+    if (g.pairs != nullptr) return g.xcd_items[x];
+    const int nc_x = g.one.n_chunks > x ? (g.one.n_chunks - x + 7) / 8 : 0;
+    return nc_x * g.one.n_tiles;
+  };
+  const int n_queues = g.pairs == nullptr && g.sync_every > 0 ? 1 : 8;
+  int qx = xcd, visited = 1;
+  int n_items = queue_items(qx);
+  int* ctr = g.counters + 8 * blockIdx.z + qx;
   double vacc = 0.0;
   // read once, before any DMA: a compiler-tracked load still pending at the
   // pipeline loop head would make the compiler drain the DMA queue there
   const int n_part = g.pairs == nullptr && g.sync_every > 0 ? *g.n_active : 0;
 
   for (;;) {
-    __syncthreads();   // the previous item's stage buffers are free again
+    __syncthreads();   // the previous item's stage buffers and row table are free again
     if (tid == 0) s_item = atomicAdd(ctr, 1);
     __syncthreads();
     const int item = s_item;
-    if (item >= n_items) break;
+    if (item >= n_items) {
+      if (visited == n_queues) break;
+      ++visited;
+      qx = (qx + 1) & 7;
+      n_items = queue_items(qx);
+      ctr = g.counters + 8 * blockIdx.z + qx;
+      continue;
+    }
     PairDesc P;
     int tile, chunk_id;
     if (g.pairs == nullptr) {
       P = g.one;
       const int m = item / P.n_tiles;
       tile = item - m * P.n_tiles;
-      chunk_id = xcd + 8 * m;
+      chunk_id = qx + 8 * m;
     } else {
       // the record holding this item, then the pair within its DM group
-      const SuperChunk* rec = g.recs + g.rec_off[xcd];
-      int lo = 0, hi = g.rec_cnt[xcd] - 1;
+      const SuperChunk* rec = g.recs + g.rec_off[qx];
+      int lo = 0, hi = g.rec_cnt[qx] - 1;
       while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (rec[mid].item0 <= item) lo = mid; else hi = mid - 1;
@@ -575,37 +602,31 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
     const int4 ti = P.tile_info[tile];
     if (ti.y == 0) continue;   // empty tile
     const int y0 = ti.x, nfl = ti.z;
+    // the tile's row table goes to LDS (one coalesced load), where the row
+    // lookups below run without a memory round trip each
+    {
+      const int2* rows_g = P.rows + (size_t)tile * P.BHmax;
+      for (int r = tid; r < P.BHmax; r += BLOCK) s_rows[r] = rows_g[r];
+    }
     const int kk = slot < P.ns ? P.slot_kk[(size_t)tile * P.ns + slot] : -1;
-    const int2* rows = P.rows + (size_t)tile * P.BHmax;
+    const int2* rows = s_rows;
 
-    float wx[RPL][PW], wy[RPL][PW];
-    int base[RPL];
+    int2 o = make_int2(0, 0), hr = make_int2(0, 0);
     if (kk >= 0) {
-      const int2 o = P.origin[kk];
-      const int2 hr = P.hrows[kk];
-      const float* W = P.weights + ((size_t)plane * P.nv + kk) * 2 * E;
+      o = P.origin[kk];
+      hr = P.hrows[kk];
+    }
+    __syncthreads();   // the row table is in LDS
+    int base[RPL];
 #pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        // patch rows outside [hr.x, hr.y) hold zero weights and are not
-        // staged: point them at any staged float (all are finite)
-        const int pr = q + LPS * i;
-        base[i] = 0;
-        if (pr >= hr.x && pr < hr.y) {
-          const int2 rw = rows[o.y + pr - y0];
-          base[i] = rw.y + (o.x - rw.x);
-        }
-#pragma unroll
-        for (int c = 0; c < PW; ++c) {
-          wx[i][c] = W[(q + LPS * i) * PW + c];
-          wy[i][c] = W[E + (q + LPS * i) * PW + c];
-        }
-      }
-    } else {
-#pragma unroll
-      for (int i = 0; i < RPL; ++i) {
-        base[i] = 0;
-#pragma unroll
-        for (int c = 0; c < PW; ++c) wx[i][c] = wy[i][c] = 0.f;
+    for (int i = 0; i < RPL; ++i) {
+      // patch rows outside [hr.x, hr.y) hold zero weights and are not
+      // staged: point them at any staged float (all are finite)
+      const int pr = q + LPS * i;
+      base[i] = 0;
+      if (kk >= 0 && pr >= hr.x && pr < hr.y) {
+        const int2 rw = rows[o.y + pr - y0];
+        base[i] = rw.y + (o.x - rw.x);
       }
     }
 
@@ -641,8 +662,29 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
       }
       voff[j] = v;
     }
-    const int a0 = chunk_id * P.chunk;
-    const int a1 = min(P.n_act, a0 + P.chunk);
+    float wx[RPL][PW], wy[RPL][PW];
+    if (kk >= 0) {
+      const float* W = P.weights + ((size_t)plane * P.nv + kk) * 2 * E;
+#pragma unroll
+      for (int i = 0; i < RPL; ++i) {
+#pragma unroll
+        for (int c = 0; c < PW; ++c) {
+          wx[i][c] = W[(q + LPS * i) * PW + c];
+          wy[i][c] = W[E + (q + LPS * i) * PW + c];
+        }
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < RPL; ++i)
+#pragma unroll
+        for (int c = 0; c < PW; ++c) wx[i][c] = wy[i][c] = 0.f;
+    }
+    // chunk = P.chunk actuators, or (P.chunk == 0) an even split of the
+    // actuators over P.n_chunks chunks
+    const int a0 = P.chunk > 0 ? chunk_id * P.chunk
+                               : (int)((long long)chunk_id * P.n_act / P.n_chunks);
+    const int a1 = P.chunk > 0 ? min(P.n_act, a0 + P.chunk)
+                               : (int)((long long)(chunk_id + 1) * P.n_act / P.n_chunks);
     const int n_grp = a1 > a0 ? (a1 - a0 + KP - 1) / KP : 0;
     // XCD sync (single pair only; E >= NST - 1 groups is guaranteed by the host)
     const bool sync_on = g.pairs == nullptr && g.sync_every > 0;
@@ -746,8 +788,7 @@ __global__ __launch_bounds__(BLOCK) void im_stream_kernel(StreamArgs g) {
     // every compiler-tracked load of the item (weights, rows) has landed
     // before the first DMA; otherwise the compiler would wait for them at
     // their first use inside the pipeline, with vmcnt(0), draining the DMA
-    // queue at every loop head.  The row search above already waited on
-    // loads issued after the weights, so this costs next to nothing.
+    // queue at every loop head.
     wait_vm(0);
     [&]<int... K>(std::integer_sequence<int, K...>) {
       ((K < n_grp && K < NST - 1 ? issue(K, stage_buf<K, STAGE_F4>(), K) : void()), ...);
@@ -1237,18 +1278,34 @@ int persistent_grid(StreamFn fn, int block) {
 }
 
 // Chunk length: enough (chunk, tile) items per workgroup for dynamic balance,
-// and chunks long enough to amortise each item's weight load.
+// chunks long enough to amortise each item's set-up, and no longer than
+// CHUNK_MAX actuators: neighbouring tiles of a chunk start together and
+// drift apart as they stream it, so short chunks keep their shared halo rows
+// in L2 (measured on the ELT workload: 32 beats 64 by 8%, and 16-48 are
+// within 3% of each other).
+constexpr int CHUNK_MAX = 32;
 int chunk_for(long act_tiles, int G) {
   long chunk = (act_tiles + 4L * G - 1) / (4L * G);
-  return (int)std::max(1L, std::min(64L, chunk));
+  return (int)std::max(1L, std::min((long)CHUNK_MAX, chunk));
+}
+
+// Chunks of a single-pair launch: as chunk_for asks, rounded up to a multiple
+// of 8 so that every XCD queue holds the same number, the actuators split
+// evenly over them (lengths differ by at most one).
+int chunks_for(int n_act, int n_tiles, int G) {
+  const long len = chunk_for((long)n_act * n_tiles, G);
+  long nc = (n_act + len - 1) / len;
+  nc = (nc + 7) / 8 * 8;
+  return (int)std::min<long>(nc, n_act);
 }
 
 StreamFn pick_fn(const Variant& v, bool vec4, bool vjp) {
   return vjp ? (vec4 ? v.vjp4 : v.vjp1) : (vec4 ? v.im4 : v.im1);
 }
 
+// chunk > 0: chunks of that many actuators; chunk == 0: n_chunks even chunks
 PairDesc pair_desc(const Plan& P, const float* ifs, int n_act, int H_in, int W_in, int nv,
-                   float* out, int chunk) {
+                   float* out, int chunk, int n_chunks = 0) {
   PairDesc pd{};
   pd.ifs = ifs;
   pd.out = out;
@@ -1266,7 +1323,7 @@ PairDesc pair_desc(const Plan& P, const float* ifs, int n_act, int H_in, int W_i
   pd.ns = P.d.NSLOT;
   pd.BHmax = P.d.BHmax;
   pd.chunk = chunk;
-  pd.n_chunks = (n_act + chunk - 1) / chunk;
+  pd.n_chunks = chunk > 0 ? (n_act + chunk - 1) / chunk : n_chunks;
   return pd;
 }
 
@@ -1282,8 +1339,8 @@ int launch_stream(const Plan& P, const float* ifs, int n_act, int H_in, int W_in
   if (G < 0) return SYNIM_E_HIP;
   if (grad && G > GMAX_VJP) return SYNIM_E_SHAPE;
   StreamArgs g{};
-  const int chunk = d.sched == SCHED_XCD ? (n_act + 7) / 8 : chunk_for((long)n_act * d.n_tiles, G);
-  g.one = pair_desc(P, ifs, n_act, H_in, W_in, nv, out, chunk);
+  const int n_chunks = d.sched == SCHED_XCD ? std::min(8, n_act) : chunks_for(n_act, d.n_tiles, G);
+  g.one = pair_desc(P, ifs, n_act, H_in, W_in, nv, out, 0, n_chunks);
   g.pairs = nullptr;
   g.counters = P.counters();
   g.scratch = P.scratch();
