@@ -78,29 +78,51 @@ __device__ __forceinline__ const PlanJob& job_of(const PlanJob& one, const PlanJ
   return jobs ? jobs[blockIdx.y] : one;
 }
 
-// Origin (patch corner) and 1/(2 n_k) of each valid subaperture.
-__global__ void plan_subaps_kernel(PlanJob one, const PlanJob* __restrict__ jobs) {
+// Origin (patch corner) and 1/(2 n_k) of each valid subaperture: one wave
+// per subaperture, its lanes splitting the haloed window's samples and the
+// subaperture's pixels (min, max and counts do not depend on the order).
+constexpr int PLAN_SUBAPS_BLOCK = 256;
+__device__ __forceinline__ double wave_min(double v) {
+  for (int o = 32; o >= 1; o >>= 1) v = fmin(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_max(double v) {
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__global__ __launch_bounds__(PLAN_SUBAPS_BLOCK) void plan_subaps_kernel(
+    PlanJob one, const PlanJob* __restrict__ jobs) {
   const PlanJob& J = job_of(one, jobs);
-  const int kk = blockIdx.x * blockDim.x + threadIdx.x;
-  if (kk >= J.nv) return;
+  const int kk = (int)((blockIdx.x * PLAN_SUBAPS_BLOCK + threadIdx.x) >> 6);
+  const int lane = threadIdx.x & 63;
+  if (kk >= J.nv) return;   // whole waves
   const MapD m = J.m_dev ? *J.m_dev : J.m;
   const int p = J.p;
   const int k = J.valid[kk];
   const int u = k % J.n_sub_x, v = k / J.n_sub_x;
   const int W = J.n_sub_x * p;
   double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
-  for (int y = v * p - 1; y <= v * p + p; ++y)
-    for (int x = u * p - 1; x <= u * p + p; ++x) {
-      double xs, ys;
-      src_xy(m, x, y, xs, ys);
-      xmin = fmin(xmin, xs);
-      xmax = fmax(xmax, xs);
-      ymin = fmin(ymin, ys);
-      ymax = fmax(ymax, ys);
-    }
+  const int hw = p + 2;   // haloed window side
+  for (int i = lane; i < hw * hw; i += 64) {
+    const int y = v * p - 1 + i / hw, x = u * p - 1 + i % hw;
+    double xs, ys;
+    src_xy(m, x, y, xs, ys);
+    xmin = fmin(xmin, xs);
+    xmax = fmax(xmax, xs);
+    ymin = fmin(ymin, ys);
+    ymax = fmax(ymax, ys);
+  }
+  xmin = wave_min(xmin);
+  ymin = wave_min(ymin);
+  xmax = wave_max(xmax);
+  ymax = wave_max(ymax);
   int nk = 0;
-  for (int y = v * p; y < v * p + p; ++y)
-    for (int x = u * p; x < u * p + p; ++x) nk += J.pupil[(size_t)y * W + x] ? 1 : 0;
+  for (int i = lane; i < p * p; i += 64) {
+    const int y = v * p + i / p, x = u * p + i % p;
+    nk += J.pupil[(size_t)y * W + x] ? 1 : 0;
+  }
+  for (int o = 32; o >= 1; o >>= 1) nk += __shfl_xor(nk, o, 64);
+  if (lane != 0) return;
   int ox = 0, oy = 0;
   if (fabs(xmin) < 1e9 && fabs(xmax) < 1e9 && fabs(ymin) < 1e9 && fabs(ymax) < 1e9) {
     ox = (int)floor(xmin);
@@ -122,14 +144,12 @@ __device__ __forceinline__ int in_sub(const uint8_t* __restrict__ pupil, int W, 
   return (x >= x0 && x < x0 + p && y >= y0 && y < y0 + p && pupil[(size_t)y * W + x]) ? 1 : 0;
 }
 
-// One thread per (valid subaperture, patch entry).  Gathers, in a fixed
-// order, every haloed-window sample q whose bilinear cell has this entry as a
-// tap.  Weights layout: [plane][kk][component x|y][PH*PW].
-__global__ void plan_weights_kernel(PlanJob one, const PlanJob* __restrict__ jobs) {
-  const PlanJob& J = job_of(one, jobs);
-  const int E = J.PH * J.PW;
-  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long)J.nv * E) return;
+// Weight patch entry gid = (valid subaperture, patch entry): gathers, in a
+// fixed order, every haloed-window sample q whose bilinear cell has this entry
+// as a tap.  Weights layout: [plane][kk][component x|y][PH*PW].  A used entry
+// widens its subaperture's row range in s_lo/s_hi (index kk - kk0).
+__device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long gid, int kk0,
+                                                  int* s_lo, int* s_hi) {
   const MapD m = J.m_dev ? *J.m_dev : J.m;
   const int p = J.p;
   // inverse of the linear part, for the window of candidate samples
@@ -193,13 +213,39 @@ __global__ void plan_weights_kernel(PlanJob one, const PlanJob* __restrict__ job
   bool used = false;
   for (int j = 0; j < J.n_planes; ++j) used = used || acc[j][0] != 0.0 || acc[j][1] != 0.0;
   if (used) {
-    atomicMin(&J.hrows[kk].x, r);
-    atomicMax(&J.hrows[kk].y, r + 1);
+    atomicMin(&s_lo[kk - kk0], r);
+    atomicMax(&s_hi[kk - kk0], r + 1);
   }
   for (int j = 0; j < J.n_planes; ++j) {
     float* w = J.weights + ((size_t)j * J.nv + kk) * 2 * E;
     w[e] = (float)(acc[j][0] * s);
     w[E + e] = (float)(acc[j][1] * s);
+  }
+}
+
+// One thread per (valid subaperture, patch entry), PLAN_WEIGHTS_BLOCK per
+// workgroup.
+constexpr int PLAN_WEIGHTS_BLOCK = 256;
+__global__ __launch_bounds__(PLAN_WEIGHTS_BLOCK) void plan_weights_kernel(
+    PlanJob one, const PlanJob* __restrict__ jobs) {
+  const PlanJob& J = job_of(one, jobs);
+  const int E = J.PH * J.PW;
+  const long g0 = (long)blockIdx.x * PLAN_WEIGHTS_BLOCK;
+  const long gid = g0 + threadIdx.x;
+  // rows holding a weight, per subaperture of this workgroup (at most
+  // PLAN_WEIGHTS_BLOCK of them, relative to the first): reduced in LDS, then
+  // one global atomic pair per subaperture and workgroup
+  __shared__ int s_lo[PLAN_WEIGHTS_BLOCK], s_hi[PLAN_WEIGHTS_BLOCK];
+  const int kk0 = (int)(g0 / E);
+  s_lo[threadIdx.x] = INT_MAX;
+  s_hi[threadIdx.x] = INT_MIN;
+  __syncthreads();
+  if (gid < (long)J.nv * E) plan_weight_entry(J, E, gid, kk0, s_lo, s_hi);
+  __syncthreads();
+  const int kk = kk0 + threadIdx.x;
+  if (kk < J.nv && s_lo[threadIdx.x] != INT_MAX) {
+    atomicMin(&J.hrows[kk].x, s_lo[threadIdx.x]);
+    atomicMax(&J.hrows[kk].y, s_hi[threadIdx.x]);
   }
 }
 
@@ -299,12 +345,29 @@ __global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
     }
   }
   __syncthreads();
-  if (tid == 0) {
-    int off = 0;
-    for (int r = 0; r < bh; ++r) {
-      J.rows[(size_t)t * J.BHmax + r] = make_int2(s_x0[r], off);
-      off += s_w[r];
+  // packed offsets: exclusive prefix sum of the row widths (Hillis-Steele in
+  // LDS over blocks of blockDim rows, carried across blocks)
+  __shared__ int s_scan[256];
+  __shared__ int s_carry;
+  if (tid == 0) s_carry = 0;
+  for (int r0 = 0; r0 < bh; r0 += blockDim.x) {
+    const int r = r0 + tid;
+    const int w = r < bh ? s_w[r] : 0;
+    s_scan[tid] = w;
+    __syncthreads();
+    for (int o = 1; o < (int)blockDim.x; o <<= 1) {
+      const int add = tid >= o ? s_scan[tid - o] : 0;
+      __syncthreads();
+      s_scan[tid] += add;
+      __syncthreads();
     }
+    if (r < bh) J.rows[(size_t)t * J.BHmax + r] = make_int2(s_x0[r], s_carry + s_scan[tid] - w);
+    __syncthreads();
+    if (tid == 0) s_carry += s_scan[blockDim.x - 1];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int off = s_carry;
     if (off > J.cap_floats) {
       atomicOr(J.status, 2);   // tile skipped: its slopes stay unwritten
       J.tile_info[t] = make_int4(0, 0, 0, 0);
@@ -548,10 +611,14 @@ im_stream_kernel(StreamArgs g) {
     const int nc_x = g.one.n_chunks > x ? (g.one.n_chunks - x + 7) / 8 : 0;
     return nc_x * g.one.n_tiles;
   };
-  const int n_queues = g.pairs == nullptr && g.sync_every > 0 ? 1 : 8;
-  int qx = xcd, visited = 1;
+  const bool may_steal = !(g.pairs == nullptr && g.sync_every > 0);
+  int qx = xcd;
   int n_items = queue_items(qx);
   int* ctr = g.counters + 8 * blockIdx.z + qx;
+  // queues other than its own that still held items when the workgroup last
+  // looked (bit i: queue xcd + 1 + i); -1 before the first look
+  int others = -1;
+  __shared__ int s_others;
   double vacc = 0.0;
   // read once, before any DMA: a compiler-tracked load still pending at the
   // pipeline loop head would make the compiler drain the DMA queue there
@@ -563,9 +630,25 @@ im_stream_kernel(StreamArgs g) {
     __syncthreads();
     const int item = s_item;
     if (item >= n_items) {
-      if (visited == n_queues) break;
-      ++visited;
-      qx = (qx + 1) & 7;
+      if (!may_steal) break;
+      if (others < 0) {
+        // one parallel look at the other seven counters (they only grow, so
+        // a queue seen exhausted stays exhausted)
+        if (tid == 0) s_others = 0;
+        __syncthreads();
+        if (tid < 7) {
+          const int x = (xcd + 1 + tid) & 7;
+          const int c = __hip_atomic_load(g.counters + 8 * blockIdx.z + x, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
+          if (c < queue_items(x)) atomicOr(&s_others, 1 << tid);
+        }
+        __syncthreads();
+        others = s_others;
+      }
+      if (others == 0) break;
+      const int i = __ffs(others) - 1;
+      others &= others - 1;
+      qx = (xcd + 1 + i) & 7;
       n_items = queue_items(qx);
       ctr = g.counters + 8 * blockIdx.z + qx;
       continue;
@@ -1230,11 +1313,15 @@ int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv
   for (int j0 = 0; j0 < n; j0 += 65535) {
     const int nj = std::min(65535, n - j0);
     const PlanJob* jt = jobs_dev ? jobs_dev + j0 : nullptr;
-    hipLaunchKernelGGL(plan_subaps_kernel, dim3((max_nv + 127) / 128, nj), dim3(128), 0, st, one,
-                       jt);
+    hipLaunchKernelGGL(plan_subaps_kernel,
+                       dim3((unsigned)(((long)max_nv * 64 + PLAN_SUBAPS_BLOCK - 1) / PLAN_SUBAPS_BLOCK),
+                            nj),
+                       dim3(PLAN_SUBAPS_BLOCK), 0, st, one, jt);
     SYNIM_HIP_TRY(hipGetLastError());
     const long nthr = (long)max_nv * max_e;
-    hipLaunchKernelGGL(plan_weights_kernel, dim3((unsigned)((nthr + 255) / 256), nj), dim3(256),
+    hipLaunchKernelGGL(plan_weights_kernel,
+                       dim3((unsigned)((nthr + PLAN_WEIGHTS_BLOCK - 1) / PLAN_WEIGHTS_BLOCK), nj),
+                       dim3(PLAN_WEIGHTS_BLOCK),
                        0, st, one, jt);
     SYNIM_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(plan_slots_kernel, dim3((unsigned)((max_slots + 255) / 256), nj),
