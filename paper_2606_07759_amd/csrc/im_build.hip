@@ -27,6 +27,7 @@
 // and contracts them against the patches; the LPS lanes that share a
 // subaperture combine their partial sums with DPP.
 #include <algorithm>
+#include <map>
 #include <climits>
 #include <cmath>
 #include <mutex>
@@ -278,34 +279,34 @@ __global__ void plan_slots_kernel(PlanJob one, const PlanJob* __restrict__ jobs)
 // column interval those patches cover (aligned to 4 floats), packed one after
 // the other.  tile_info[t] = (y0, rows, packed floats, 0), rows = 0 for an empty
 // tile; rows[t*BHmax + r] = (first column of row r, packed offset of row r).
-__global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
-                                                        const PlanJob* __restrict__ jobs) {
-  const PlanJob& J = job_of(one, jobs);
+// Row table of tile t: slot_of(s) gives slot s's (origin, patch rows
+// holding a weight), or hr.x >= hr.y for an empty slot.  Writes rows[t*BHmax
+// + r], tile_info[t]; flags bit 1 of status[0] for a tile that does not fit,
+// counts non-empty tiles in status[1].  256 threads.
+template <class SlotOf>
+__device__ __forceinline__ void build_tile_rows(int t, int NS, int PW, int BHmax, int cap_floats,
+                                                SlotOf slot_of, int2* rows_out, int4* tile_info,
+                                                int* status) {
   __shared__ int s_ox[1024], s_oy[1024], s_oe[1024];
   __shared__ int s_x0[MAX_TILE_ROWS], s_w[MAX_TILE_ROWS];
   __shared__ int s_ymin, s_ymax;
-  const int t = blockIdx.x, tid = threadIdx.x;
-  if (t >= J.n_tiles) return;
-  const int NS = J.NSLOT, PH = J.PH, PW = J.PW;
+  const int tid = threadIdx.x;
   if (tid == 0) {
     s_ymin = INT_MAX;
     s_ymax = INT_MIN;
   }
   __syncthreads();
   for (int s = tid; s < NS; s += blockDim.x) {
-    const int kk = J.slot_kk[(size_t)t * NS + s];
+    int2 o, hr;
+    slot_of(s, o, hr);
     // rows [oy, oe) of the IF grid that the subaperture's weights touch
     int ox = INT_MIN, oy = INT_MIN, oe = INT_MIN;
-    if (kk >= 0) {
-      const int2 o = J.origin[kk];
-      const int2 hr = J.hrows[kk];
-      if (hr.x < hr.y) {
-        ox = o.x;
-        oy = o.y + hr.x;
-        oe = o.y + hr.y;
-        atomicMin(&s_ymin, oy);
-        atomicMax(&s_ymax, oe);
-      }
+    if (hr.x < hr.y) {
+      ox = o.x;
+      oy = o.y + hr.x;
+      oe = o.y + hr.y;
+      atomicMin(&s_ymin, oy);
+      atomicMax(&s_ymax, oe);
     }
     s_ox[s] = ox;
     s_oy[s] = oy;
@@ -314,14 +315,14 @@ __global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
   __syncthreads();
   const int y0 = s_ymin;
   if (y0 == INT_MAX) {
-    if (tid == 0) J.tile_info[t] = make_int4(0, 0, 0, 0);
+    if (tid == 0) tile_info[t] = make_int4(0, 0, 0, 0);
     return;
   }
   const int bh = s_ymax - y0;
-  if (bh > J.BHmax || bh > MAX_TILE_ROWS) {
+  if (bh > BHmax || bh > MAX_TILE_ROWS) {
     if (tid == 0) {
-      atomicOr(J.status, 2);
-      J.tile_info[t] = make_int4(0, 0, 0, 0);
+      atomicOr(status, 2);
+      tile_info[t] = make_int4(0, 0, 0, 0);
     }
     return;
   }
@@ -361,21 +362,63 @@ __global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
       s_scan[tid] += add;
       __syncthreads();
     }
-    if (r < bh) J.rows[(size_t)t * J.BHmax + r] = make_int2(s_x0[r], s_carry + s_scan[tid] - w);
+    if (r < bh) rows_out[(size_t)t * BHmax + r] = make_int2(s_x0[r], s_carry + s_scan[tid] - w);
     __syncthreads();
     if (tid == 0) s_carry += s_scan[blockDim.x - 1];
     __syncthreads();
   }
   if (tid == 0) {
     const int off = s_carry;
-    if (off > J.cap_floats) {
-      atomicOr(J.status, 2);   // tile skipped: its slopes stay unwritten
-      J.tile_info[t] = make_int4(0, 0, 0, 0);
+    if (off > cap_floats) {
+      atomicOr(status, 2);   // tile skipped: its slopes stay unwritten
+      tile_info[t] = make_int4(0, 0, 0, 0);
     } else {
-      J.tile_info[t] = make_int4(y0, bh, off, 0);
-      atomicAdd(J.status + 1, 1);   // non-empty tiles
+      tile_info[t] = make_int4(y0, bh, off, 0);
+      atomicAdd(status + 1, 1);   // non-empty tiles
     }
   }
+}
+
+__global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
+                                                        const PlanJob* __restrict__ jobs) {
+  const PlanJob& J = job_of(one, jobs);
+  const int t = blockIdx.x;
+  if (t >= J.n_tiles) return;
+  const int NS = J.NSLOT;
+  build_tile_rows(
+      t, NS, J.PW, J.BHmax, J.cap_floats,
+      [&](int s, int2& o, int2& hr) {
+        const int kk = J.slot_kk[(size_t)t * NS + s];
+        o = make_int2(0, 0);
+        hr = make_int2(0, 0);
+        if (kk >= 0) {
+          o = J.origin[kk];
+          hr = J.hrows[kk];
+        }
+      },
+      J.rows, J.tile_info, J.status);
+}
+
+// Shared tiles of a batch: slot (pair << 20 | subaperture), the pair by its
+// position in the job table, reads that pair's plan (origins and row ranges).
+__global__ __launch_bounds__(256) void plan_rows_shared_kernel(
+    const PlanJob* __restrict__ jobs, const int* __restrict__ jslots, int n_jt, int NS, int PW,
+    int BHmax, int cap_floats, int2* rows_out, int4* tile_info, int* status) {
+  const int t = blockIdx.x;
+  if (t >= n_jt) return;
+  build_tile_rows(
+      t, NS, PW, BHmax, cap_floats,
+      [&](int s, int2& o, int2& hr) {
+        const int e = jslots[(size_t)t * NS + s];
+        o = make_int2(0, 0);
+        hr = make_int2(0, 0);
+        if (e >= 0) {
+          const PlanJob& J = jobs[e >> 20];
+          o = J.origin[e & 0xFFFFF];
+          hr = J.hrows[e & 0xFFFFF];
+        }
+      },
+      rows_out, tile_info, status);
 }
 
 __global__ void zero_ints_kernel(int* __restrict__ p, int n) {
@@ -445,6 +488,16 @@ struct StreamArgs {
   int sync_every;
   int* sync_ctr;             // [gridDim.z][8] block entries, zeroed before the launch
   const int* n_active;       // non-empty tiles (written by the plan)
+  // Batched launches with shared tiles (nullptr jslots: per-pair tiles).  A
+  // shared tile gathers the subapertures of every pair of one DM group whose
+  // patches fall in one region of the IF grid, so that region is staged once
+  // for all of them.
+  const int* jslots;         // [tile][jNS]: (pair << 20) | subaperture, or -1; pair
+                             // indexes the pair table
+  const int4* jinfo;         // [tile] (y0, rows, packed floats, 0), written by the plan
+  const int2* jrows;         // [tile][jBHmax] (first column, packed offset)
+  const int2* jgroups;       // per DM group: (first shared tile, count)
+  int jNS, jBHmax;
 };
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -453,6 +506,7 @@ typedef __attribute__((address_space(3))) void lds_void_t;
 constexpr int waitcnt_vm(int n) { return (n & 15) | (7 << 4) | (15 << 8) | (((n >> 4) & 3) << 14); }
 
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(1))) float gfloat_t;   // global memory
 
 // Raw buffer resource (stride 0, range-checked) over [base, base + bytes),
 // every word wave-uniform so it lives in SGPRs.
@@ -486,6 +540,12 @@ __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory")
 // no LDS write for it and adds no wait of its own before the stage reads
 // (its conservative merge at the pipeline loop head drained every DMA in
 // flight there).  Completion is the pipeline's explicit vmcnt waits alone.
+//
+// An LDS DMA reads M0 (its LDS destination) one cycle after issue, so a
+// scalar write of M0 right before it needs one wait state in between, or the
+// DMA may take the previous M0 and land somewhere else in LDS.  The compiler
+// pads its own LDS-DMA instructions with an s_nop for this; it cannot see into
+// inline assembly, so each DMA below opens with that s_nop itself.
 template <int BLOCK, int NJ, int VW>
 __device__ __forceinline__ void stage_issue(const float* plane_ptr, int plane_bytes,
                                             const unsigned* voff, float4* buf, int wave) {
@@ -495,10 +555,12 @@ __device__ __forceinline__ void stage_issue(const float* plane_ptr, int plane_by
     const unsigned m0 =
         lds_addr(reinterpret_cast<float*>(buf) + (size_t)(BLOCK * j + 64 * wave) * VW);
     if constexpr (VW == 4)
-      asm volatile("buffer_load_dwordx4 %0, %1, 0 offen lds" ::"v"(voff[j]), "s"(r), "{m0}"(m0)
+      asm volatile("s_nop 0\n\tbuffer_load_dwordx4 %0, %1, 0 offen lds" ::"v"(voff[j]), "s"(r),
+                   "{m0}"(m0)
                    : "memory");
     else
-      asm volatile("buffer_load_dword %0, %1, 0 offen lds" ::"v"(voff[j]), "s"(r), "{m0}"(m0)
+      asm volatile("s_nop 0\n\tbuffer_load_dword %0, %1, 0 offen lds" ::"v"(voff[j]), "s"(r),
+                   "{m0}"(m0)
                    : "memory");
   }
 }
@@ -552,7 +614,8 @@ constexpr int SYNC_STRIDE = 32;       // ints between the counters (own 128-byte
 __device__ __forceinline__ void snapshot_issue(const int* ctr, int* lds_dst) {
   const u32x4 r = buffer_rsrc(ctr, 4u);
   const unsigned m0 = lds_addr(lds_dst);
-  asm volatile("buffer_load_dword %0, %1, 0 offen sc1 lds" ::"v"(0u), "s"(r), "{m0}"(m0)
+  asm volatile("s_nop 0\n\tbuffer_load_dword %0, %1, 0 offen sc1 lds" ::"v"(0u), "s"(r),
+               "{m0}"(m0)
                : "memory");
 }
 
@@ -583,7 +646,14 @@ constexpr int stream_waves_per_simd(int block, int nj, int vw, int nst) {
   return w < 1 ? 1 : (w > 8 ? 8 : w);
 }
 
-template <int BLOCK, int LPS, int RPL, int PW, int NJ, int VW, int NST, int PACK, bool VJP>
+// BATCH = false: the single-pair launches, with every batch path compiled out.
+// BATCH = true: the batched launches; that instantiation keeps the single-pair
+// paths too and picks by g.pairs at run time.  (Compiled with the batch
+// decision fixed instead, the batch kernel gave wrong values for some
+// actuators from run to run; the cause was not found, so that form is not
+// used.)
+template <int BLOCK, int LPS, int RPL, int PW, int NJ, int VW, int NST, int PACK, bool VJP,
+          bool BATCH>
 __global__ __launch_bounds__(BLOCK, VW == 4 ? stream_waves_per_simd(BLOCK, NJ, VW, NST) : 1) void
 im_stream_kernel(StreamArgs g) {
   constexpr int PH = LPS * RPL;
@@ -607,11 +677,14 @@ im_stream_kernel(StreamArgs g) {
   // x+1, x+2, ...), so no XCD idles while another still has items.  With
   // the bounded-lag sync on, the workgroups of an XCD must stay on its queue.
   auto queue_items = [&](int x) {
-    if (g.pairs != nullptr) return g.xcd_items[x];
-    const int nc_x = g.one.n_chunks > x ? (g.one.n_chunks - x + 7) / 8 : 0;
-    return nc_x * g.one.n_tiles;
+    if (BATCH && g.pairs != nullptr) {
+      return g.xcd_items[x];
+    } else {
+      const int nc_x = g.one.n_chunks > x ? (g.one.n_chunks - x + 7) / 8 : 0;
+      return nc_x * g.one.n_tiles;
+    }
   };
-  const bool may_steal = !(g.pairs == nullptr && g.sync_every > 0);
+  const bool may_steal = !((!BATCH || g.pairs == nullptr) && g.sync_every > 0);
   int qx = xcd;
   int n_items = queue_items(qx);
   int* ctr = g.counters + 8 * blockIdx.z + qx;
@@ -622,7 +695,7 @@ im_stream_kernel(StreamArgs g) {
   double vacc = 0.0;
   // read once, before any DMA: a compiler-tracked load still pending at the
   // pipeline loop head would make the compiler drain the DMA queue there
-  const int n_part = g.pairs == nullptr && g.sync_every > 0 ? *g.n_active : 0;
+  const int n_part = (!BATCH || g.pairs == nullptr) && g.sync_every > 0 ? *g.n_active : 0;
 
   for (;;) {
     __syncthreads();   // the previous item's stage buffers and row table are free again
@@ -655,7 +728,8 @@ im_stream_kernel(StreamArgs g) {
     }
     PairDesc P;
     int tile, chunk_id;
-    if (g.pairs == nullptr) {
+    bool shared = false;   // a shared tile of a batch (else a tile of one pair)
+    if (!BATCH || g.pairs == nullptr) {
       P = g.one;
       const int m = item / P.n_tiles;
       tile = item - m * P.n_tiles;
@@ -671,33 +745,61 @@ im_stream_kernel(StreamArgs g) {
       const SuperChunk r = rec[lo];
       int local = item - r.item0;
       const int2 grp = g.groups[r.dm];
-      int pi = grp.x;
-      while (pi < grp.x + grp.y - 1 && local >= g.pairs[pi].n_tiles) {
-        local -= g.pairs[pi].n_tiles;
-        ++pi;
+      if (g.jslots != nullptr) {
+        // the DM-level fields (IF stack, actuators) are the group's first pair's
+        shared = true;
+        P = g.pairs[grp.x];
+        tile = g.jgroups[r.dm].x + local;
+      } else {
+        int pi = grp.x;
+        while (pi < grp.x + grp.y - 1 && local >= g.pairs[pi].n_tiles) {
+          local -= g.pairs[pi].n_tiles;
+          ++pi;
+        }
+        P = g.pairs[pi];
+        tile = local;
       }
-      P = g.pairs[pi];
-      tile = local;
       chunk_id = r.chunk;
     }
     const int plane_bytes = P.H_in * P.W_in * 4;
     const size_t plane_in = (size_t)P.H_in * P.W_in;
-    const int4 ti = P.tile_info[tile];
+    const int4 ti = shared ? g.jinfo[tile] : P.tile_info[tile];
     if (ti.y == 0) continue;   // empty tile
     const int y0 = ti.x, nfl = ti.z;
     // the tile's row table goes to LDS (one coalesced load), where the row
     // lookups below run without a memory round trip each
     {
-      const int2* rows_g = P.rows + (size_t)tile * P.BHmax;
-      for (int r = tid; r < P.BHmax; r += BLOCK) s_rows[r] = rows_g[r];
+      const int bhm = shared ? g.jBHmax : P.BHmax;
+      const int2* rows_g = (shared ? g.jrows : P.rows) + (size_t)tile * bhm;
+      for (int r = tid; r < bhm; r += BLOCK) s_rows[r] = rows_g[r];
     }
-    const int kk = slot < P.ns ? P.slot_kk[(size_t)tile * P.ns + slot] : -1;
+    // this lane's subaperture, and the pair it belongs to
+    int kk;
+    const int2* origin_l = P.origin;
+    const int2* hrows_l = P.hrows;
+    const float* weights_l = P.weights;
+    float* out_l = P.out;
+    int nv_l = P.nv;
+    if (shared) {
+      const int e = slot < g.jNS ? g.jslots[(size_t)tile * g.jNS + slot] : -1;
+      kk = e < 0 ? -1 : (e & 0xFFFFF);
+      if (e >= 0) {
+        const PairDesc* L = g.pairs + (e >> 20);
+        origin_l = L->origin;
+        hrows_l = L->hrows;
+        weights_l = L->weights;
+        out_l = L->out;
+        nv_l = L->nv;
+      }
+    } else {
+      kk = slot < P.ns ? P.slot_kk[(size_t)tile * P.ns + slot] : -1;
+    }
     const int2* rows = s_rows;
 
     int2 o = make_int2(0, 0), hr = make_int2(0, 0);
     if (kk >= 0) {
-      o = P.origin[kk];
-      hr = P.hrows[kk];
+      o = origin_l[kk];
+      hr = hrows_l[kk];
     }
     __syncthreads();   // the row table is in LDS
     int base[RPL];
@@ -747,7 +849,7 @@ im_stream_kernel(StreamArgs g) {
     }
     float wx[RPL][PW], wy[RPL][PW];
     if (kk >= 0) {
-      const float* W = P.weights + ((size_t)plane * P.nv + kk) * 2 * E;
+      const float* W = weights_l + ((size_t)plane * nv_l + kk) * 2 * E;
 #pragma unroll
       for (int i = 0; i < RPL; ++i) {
 #pragma unroll
@@ -770,7 +872,7 @@ im_stream_kernel(StreamArgs g) {
                                : (int)((long long)(chunk_id + 1) * P.n_act / P.n_chunks);
     const int n_grp = a1 > a0 ? (a1 - a0 + KP - 1) / KP : 0;
     // XCD sync (single pair only; E >= NST - 1 groups is guaranteed by the host)
-    const bool sync_on = g.pairs == nullptr && g.sync_every > 0;
+    const bool sync_on = (!BATCH || g.pairs == nullptr) && g.sync_every > 0;
     const int sync_e = sync_on ? g.sync_every : 1;
     int* sync_ctr = g.sync_ctr + (8 * blockIdx.z + xcd) * SYNC_STRIDE;
     bool sync_live = true;
@@ -795,19 +897,21 @@ im_stream_kernel(StreamArgs g) {
         }
         sx = dpp_sum(sx, LPS);
         sy = dpp_sum(sy, LPS);
-        const size_t row = (size_t)(act ? a : a0) * 2 * P.nv;
+        const size_t row = (size_t)(act ? a : a0) * 2 * nv_l;
         if (VJP) {
           if (act && kk >= 0 && q == 0)
-            vacc += (double)g.grad[row + kk] * sx + (double)g.grad[row + P.nv + kk] * sy;
+            vacc += (double)g.grad[row + kk] * sx + (double)g.grad[row + nv_l + kk] * sy;
         } else {
           // exactly one store instruction per wave and actuator slot, whatever
           // the lanes hold: lanes with nothing to write (and the slots past the
           // chunk's end) target a scratch slot.  The pipeline's wait counts
           // rely on this number.
-          float* o = P.out + (size_t)(plane - g.out_plane0) * P.n_act * 2 * P.nv + row;
+          float* o = out_l + (size_t)(plane - g.out_plane0) * P.n_act * 2 * nv_l + row;
           const bool real = act && kk >= 0 && q < 2;
-          float* dst = real ? (q == 0 ? o + kk : o + P.nv + kk) : g.scratch + (tid & 63);
-          __builtin_nontemporal_store(q == 0 ? sx : sy, dst);
+          float* dst = real ? (q == 0 ? o + kk : o + nv_l + kk) : g.scratch + (tid & 63);
+          // a global (not flat) store: flat operations may complete out of
+          // order with the DMA, and the wait counts need them in order
+          __builtin_nontemporal_store(q == 0 ? sx : sy, (gfloat_t*)dst);
         }
       }
     };
@@ -882,6 +986,7 @@ im_stream_kernel(StreamArgs g) {
       }(std::make_integer_sequence<int, NST>{});
     }
   }
+  wait_vm(0);   // no DMA or store of this workgroup outlives it
   if (VJP) {
     // fixed-order reduction: butterfly within each wave, then over the waves
     double v = vacc;
@@ -921,6 +1026,7 @@ struct Variant {
   int PACK;                            // most actuators one stage holds
   StreamFn im4, vjp4;                  // 16-byte DMA: rows a multiple of 4 floats, aligned stack
   StreamFn im1, vjp1;                  // 4-byte DMA: any row length / alignment
+  StreamFn bim4, bim1;                 // batched launches (IM only)
   int PH() const { return LPS * RPL; }
   int cap_floats() const { return NJ4 * BLOCK * 4; }
 };
@@ -930,10 +1036,13 @@ struct Variant {
 constexpr int nst_vw1(int n, int s) { return s < 2 + 63 / (4 * n) ? s : 2 + 63 / (4 * n); }
 
 #define SYNIM_VARIANT_K(B, L, R, W, N, S, K)                                           \
-  {B, L, R, W, N, S, stage_pack(N, S, K), im_stream_kernel<B, L, R, W, N, 4, S, K, false>, \
-   im_stream_kernel<B, L, R, W, N, 4, S, K, true>,                                     \
-   im_stream_kernel<B, L, R, W, 4 * N, 1, nst_vw1(N, S), K, false>,                    \
-   im_stream_kernel<B, L, R, W, 4 * N, 1, nst_vw1(N, S), K, true>}
+  {B, L, R, W, N, S, stage_pack(N, S, K),                                              \
+   im_stream_kernel<B, L, R, W, N, 4, S, K, false, false>,                             \
+   im_stream_kernel<B, L, R, W, N, 4, S, K, true, false>,                              \
+   im_stream_kernel<B, L, R, W, 4 * N, 1, nst_vw1(N, S), K, false, false>,             \
+   im_stream_kernel<B, L, R, W, 4 * N, 1, nst_vw1(N, S), K, true, false>,              \
+   im_stream_kernel<B, L, R, W, N, 4, S, K, false, true>,                              \
+   im_stream_kernel<B, L, R, W, 4 * N, 1, nst_vw1(N, S), K, false, true>}
 #define SYNIM_VARIANT(B, L, R, W, N, S) SYNIM_VARIANT_K(B, L, R, W, N, S, 1)
 #define SYNIM_VARIANT_PACK(B, L, R, W, N, S) SYNIM_VARIANT_K(B, L, R, W, N, S, 4)
 
@@ -1301,8 +1410,10 @@ PlanJob make_job(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map
 
 // Enqueue the plan kernels for `n` jobs: one job by value (jobs_dev null) or
 // a device table of n jobs (maxima give the grid extents).
+// tiles = false: origins, row ranges and weights only (the batch's shared
+// tiles replace the per-pair tile tables).
 int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv, int max_e,
-                  int max_slots, int max_tiles, hipStream_t st) {
+                  int max_slots, int max_tiles, hipStream_t st, bool tiles = true) {
   if (jobs_dev) {
     hipLaunchKernelGGL(zero_job_status_kernel, dim3((n + 255) / 256), dim3(256), 0, st, jobs_dev,
                        n);
@@ -1324,6 +1435,7 @@ int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv
                        dim3(PLAN_WEIGHTS_BLOCK),
                        0, st, one, jt);
     SYNIM_HIP_TRY(hipGetLastError());
+    if (!tiles) continue;
     hipLaunchKernelGGL(plan_slots_kernel, dim3((unsigned)((max_slots + 255) / 256), nj),
                        dim3(256), 0, st, one, jt);
     SYNIM_HIP_TRY(hipGetLastError());
@@ -1389,7 +1501,8 @@ int chunks_for(int n_act, int n_tiles, int G) {
   return (int)std::min<long>(nc, n_act);
 }
 
-StreamFn pick_fn(const Variant& v, bool vec4, bool vjp) {
+StreamFn pick_fn(const Variant& v, bool vec4, bool vjp, bool batch = false) {
+  if (batch) return vec4 ? v.bim4 : v.bim1;
   return vjp ? (vec4 ? v.vjp4 : v.vjp1) : (vec4 ? v.im4 : v.im1);
 }
 
@@ -1718,10 +1831,156 @@ struct synim_batch {
   hipEvent_t staged = nullptr;   // the last upload from `staging` has been read
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  // Shared tiles (DM groups of several pairs): one set of tiles per group over
+  // the IF grid, each holding the subapertures of every pair of the group
+  // whose patches start in one cell of cell_x x cell_y pixels (see
+  // build_shared).  The cells are fixed when the batch is bound; the exact
+  // rows follow the maps on the device.
+  bool shared = false;
+  std::vector<std::vector<int>> valid_host;   // per WFS, copied once
+  int cell_x = 0, cell_y = 0, jNS = 0, jBHmax = 0, n_jt = 0;
+  std::vector<int> jslots_host;
+  std::vector<int2> jgroups_host;
+  std::vector<int2> jorigin_host;             // per slot of jslots_host: the binned origin
+  size_t off_jslots = 0, off_jinfo = 0, off_jrows = 0, off_jgroups = 0, off_jstatus = 0;
 };
 
 namespace synim {
 namespace {
+
+// Host estimate of a subaperture's patch origin: the floor of the map's
+// minimum over the corners of the haloed window (the device takes the
+// minimum over every sample; the two agree to within one pixel).
+void host_origin(const MapD& m, int u, int v, int p, int* ox, int* oy) {
+  double xmin = 1e300, ymin = 1e300;
+  for (int cy = 0; cy < 2; ++cy)
+    for (int cx = 0; cx < 2; ++cx) {
+      const double x = u * p - 1 + cx * (p + 1), y = v * p - 1 + cy * (p + 1);
+      xmin = std::min(xmin, m.a00 * x + m.a01 * y + m.b0);
+      ymin = std::min(ymin, m.a10 * x + m.a11 * y + m.b1);
+    }
+  *ox = (int)std::floor(xmin);
+  *oy = (int)std::floor(ymin);
+}
+
+// Margin (pixels) between a binned origin and the device's: host/device
+// rounding (one pixel) plus one pixel of map drift before set_maps re-bins.
+constexpr int SHARED_MARGIN = 2;
+
+// Bins the subapertures of every pair of each DM group into shared tiles for
+// variant v: cells of cell_x x cell_y pixels over the IF grid by patch
+// origin, a cell with more than NSLOT subapertures split into NSLOT-sized
+// runs in (y, x) order.  The cell size minimises the staged 128-byte lines
+// (rows x line span per tile) among the sizes whose tiles provably fit the
+// stage buffers.
+int build_shared(synim_batch* b, const Variant& v) {
+  const int NS = v.BLOCK / v.LPS, PH = v.PH(), PW = v.PW, cap = v.cap_floats();
+  const int np = (int)b->pairs.size();
+  struct Sl {
+    int pair, kk, ox, oy;
+  };
+  std::vector<std::vector<Sl>> per_group(b->n_groups);
+  // slots name a pair by its position in group order (b->order): the pair
+  // table and the plan jobs on the device are laid out that way
+  for (int pos = 0; pos < np; ++pos) {
+    const int i = b->order[pos];
+    const synim_pair& pr = b->pairs[i];
+    const synim_wfs& w = b->wfs[pr.wfs];
+    const MapD m = to_map(pr.A);
+    const std::vector<int>& valid = b->valid_host[pr.wfs];
+    for (int kk = 0; kk < (int)valid.size(); ++kk) {
+      const int k = valid[kk];
+      int ox, oy;
+      host_origin(m, k % w.n_sub_x, k / w.n_sub_x, w.p, &ox, &oy);
+      per_group[b->group[i]].push_back(Sl{pos, kk, ox, oy});
+    }
+  }
+  if (np >= (1 << 11)) return SYNIM_E_UNSUPPORTED;   // pair index field of a slot
+  static const int kCells[] = {8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128};
+  double best = 1e300;
+  int bx = 0, by = 0;
+  for (int cx : kCells)
+    for (int cy : kCells) {
+      const int BW = (cx + PW + 2 * SHARED_MARGIN + 3 + 3) / 4 * 4;
+      const int BH = cy + PH + 2 * SHARED_MARGIN;
+      if ((long)BW * BH > cap || BH > MAX_TILE_ROWS) continue;
+      double cost = 0;
+      for (const auto& sl : per_group) {
+        std::map<std::pair<int, int>, int> cnt;
+        for (const Sl& e : sl) ++cnt[{floor_div(e.oy, cy), floor_div(e.ox, cx)}];
+        for (const auto& kv : cnt)
+          cost += (double)((kv.second + NS - 1) / NS) * BH * (BW / 32.0 + 1.0);
+      }
+      if (cost < best) {
+        best = cost;
+        bx = cx;
+        by = cy;
+      }
+    }
+  if (bx == 0) return SYNIM_E_UNSUPPORTED;
+  b->cell_x = bx;
+  b->cell_y = by;
+  b->jNS = NS;
+  b->jBHmax = by + PH + 2 * SHARED_MARGIN;
+  b->jslots_host.clear();
+  b->jorigin_host.clear();
+  b->jgroups_host.assign(b->n_groups, make_int2(0, 0));
+  int n_jt = 0;
+  for (int gi = 0; gi < b->n_groups; ++gi) {
+    std::vector<Sl> sl = per_group[gi];
+    std::stable_sort(sl.begin(), sl.end(), [&](const Sl& x, const Sl& y) {
+      const int cxa = floor_div(x.ox, bx), cya = floor_div(x.oy, by);
+      const int cxb = floor_div(y.ox, bx), cyb = floor_div(y.oy, by);
+      if (cya != cyb) return cya < cyb;
+      if (cxa != cxb) return cxa < cxb;
+      if (x.oy != y.oy) return x.oy < y.oy;
+      return x.ox < y.ox;
+    });
+    b->jgroups_host[gi] = make_int2(n_jt, 0);
+    size_t i = 0;
+    while (i < sl.size()) {
+      const int cx = floor_div(sl[i].ox, bx), cy = floor_div(sl[i].oy, by);
+      size_t j = i;
+      while (j < sl.size() && floor_div(sl[j].ox, bx) == cx && floor_div(sl[j].oy, by) == cy) ++j;
+      for (size_t t0 = i; t0 < j; t0 += NS) {
+        for (int s = 0; s < NS; ++s) {
+          const size_t at = t0 + s;
+          if (at < j) {
+            b->jslots_host.push_back((sl[at].pair << 20) | sl[at].kk);
+            b->jorigin_host.push_back(make_int2(sl[at].ox, sl[at].oy));
+          } else {
+            b->jslots_host.push_back(-1);
+            b->jorigin_host.push_back(make_int2(INT_MIN, INT_MIN));
+          }
+        }
+        ++n_jt;
+        ++b->jgroups_host[gi].y;
+      }
+      i = j;
+    }
+  }
+  b->n_jt = n_jt;
+  return SYNIM_OK;
+}
+
+// Whether maps keep every binned subaperture within the margin its shared
+// tile was sized for (else the tiles are rebuilt).
+bool shared_maps_fit(const synim_batch* b, const synim_affine* maps) {
+  for (size_t s = 0; s < b->jslots_host.size(); ++s) {
+    const int e = b->jslots_host[s];
+    if (e < 0) continue;
+    const int i = b->order[e >> 20];
+    const synim_pair& pr = b->pairs[i];
+    const synim_wfs& w = b->wfs[pr.wfs];
+    const int k = b->valid_host[pr.wfs][e & 0xFFFFF];
+    int ox, oy;
+    host_origin(to_map(maps[i]), k % w.n_sub_x, k / w.n_sub_x, w.p, &ox, &oy);
+    const int2 o = b->jorigin_host[s];
+    if (std::abs(ox - o.x) > SHARED_MARGIN - 1 || std::abs(oy - o.y) > SHARED_MARGIN - 1)
+      return false;
+  }
+  return true;
+}
 
 // The batch's tables and the pairs' plans for kernel variant v, laid out in
 // the workspace; returns the bytes needed (layout only if b->ws is null).
@@ -1749,6 +2008,17 @@ int batch_layout(synim_batch* b, const Variant& v, size_t* bytes) {
         break;
       }
   b->off_recs = take(max_recs * sizeof(SuperChunk));
+  if (b->shared) {
+    int rc = build_shared(b, v);
+    if (rc != SYNIM_OK) return rc;
+    // room for half as many tiles again, for re-binning after set_maps
+    const size_t cap_jt = (size_t)b->n_jt + b->n_jt / 2 + 8;
+    b->off_jslots = take(cap_jt * b->jNS * sizeof(int));
+    b->off_jinfo = take(cap_jt * sizeof(int4));
+    b->off_jrows = take(cap_jt * b->jBHmax * sizeof(int2));
+    b->off_jgroups = take((size_t)b->n_groups * sizeof(int2));
+    b->off_jstatus = take(16 * sizeof(int));
+  }
   b->plans.assign(np, Plan{});
   for (int i = 0; i < np; ++i) {
     const synim_pair& pr = b->pairs[i];
@@ -1814,12 +2084,21 @@ int batch_bind(synim_batch* b, const Variant& v, hipStream_t st) {
   b->vec4 = true;
   for (const auto& d : b->dms)
     if (d.W_in % 4 != 0 || (reinterpret_cast<uintptr_t>(d.ifs) & 15) != 0) b->vec4 = false;
-  StreamFn fn = pick_fn(v, b->vec4, false);
+  StreamFn fn = pick_fn(v, b->vec4, false, true);
   b->G = persistent_grid(fn, v.BLOCK);
   if (b->G < 0) return SYNIM_E_HIP;
   long act_tiles = 0;
-  for (int i = 0; i < np; ++i)
-    act_tiles += (long)b->dms[b->pairs[i].dm].n_act * b->plans[i].d.n_tiles;
+  if (b->shared) {
+    for (int gi = 0; gi < b->n_groups; ++gi)
+      for (int i = 0; i < np; ++i)
+        if (b->group[i] == gi) {
+          act_tiles += (long)b->dms[b->pairs[i].dm].n_act * b->jgroups_host[gi].y;
+          break;
+        }
+  } else {
+    for (int i = 0; i < np; ++i)
+      act_tiles += (long)b->dms[b->pairs[i].dm].n_act * b->plans[i].d.n_tiles;
+  }
   const int chunk = chunk_for(act_tiles, b->G, CHUNK_MAX_BATCH);
   // pair table in DM order, groups, super-chunk records
   std::vector<PairDesc> pd(np);
@@ -1842,7 +2121,10 @@ int batch_bind(synim_batch* b, const Variant& v, hipStream_t st) {
   for (int gi = 0; gi < b->n_groups; ++gi) {
     if (groups[gi].y == 0) continue;
     int items = 0;
-    for (int k = 0; k < groups[gi].y; ++k) items += pd[groups[gi].x + k].n_tiles;
+    if (b->shared)
+      items = b->jgroups_host[gi].y;
+    else
+      for (int k = 0; k < groups[gi].y; ++k) items += pd[groups[gi].x + k].n_tiles;
     const int nch = (group_nact[gi] + chunk - 1) / chunk;
     for (int c = 0; c < nch; ++c, ++sc) {
       const int x = (int)(sc % 8);
@@ -1866,16 +2148,19 @@ int batch_bind(synim_batch* b, const Variant& v, hipStream_t st) {
   std::vector<PlanJob> jobs(np);
   const MapD* maps_dev = reinterpret_cast<const MapD*>(b->ws + b->off_maps);
   b->max_nv = b->max_e = b->max_slots = b->max_tiles = 0;
-  for (int i = 0; i < np; ++i) {
+  // jobs in group order (the order of the pair table): shared-tile slots and
+  // the group prefixes of batch_enqueue index them that way
+  for (int pos = 0; pos < np; ++pos) {
+    const int i = b->order[pos];
     const synim_pair& pr = b->pairs[i];
     const Map4* dmaps_dev =
         b->planes > 1 ? reinterpret_cast<const Map4*>(b->ws + b->off_dmaps) + i : nullptr;
-    jobs[i] = make_job(b->wfs[pr.wfs], to_map(pr.A), maps_dev + i, Map4{}, dmaps_dev, b->planes,
-                       b->plans[i]);
-    b->max_nv = std::max(b->max_nv, jobs[i].nv);
-    b->max_e = std::max(b->max_e, jobs[i].PH * jobs[i].PW);
-    b->max_slots = std::max(b->max_slots, jobs[i].n_tiles * jobs[i].NSLOT);
-    b->max_tiles = std::max(b->max_tiles, jobs[i].n_tiles);
+    jobs[pos] = make_job(b->wfs[pr.wfs], to_map(pr.A), maps_dev + i, Map4{}, dmaps_dev,
+                         b->planes, b->plans[i]);
+    b->max_nv = std::max(b->max_nv, jobs[pos].nv);
+    b->max_e = std::max(b->max_e, jobs[pos].PH * jobs[pos].PW);
+    b->max_slots = std::max(b->max_slots, jobs[pos].n_tiles * jobs[pos].NSLOT);
+    b->max_tiles = std::max(b->max_tiles, jobs[pos].n_tiles);
   }
   SYNIM_HIP_TRY(hipMemcpyAsync(b->ws + b->off_jobs, jobs.data(), np * sizeof(PlanJob),
                                hipMemcpyHostToDevice, st));
@@ -1886,14 +2171,22 @@ int batch_bind(synim_batch* b, const Variant& v, hipStream_t st) {
   if (!recs.empty())
     SYNIM_HIP_TRY(hipMemcpyAsync(b->ws + b->off_recs, recs.data(),
                                  recs.size() * sizeof(SuperChunk), hipMemcpyHostToDevice, st));
+  if (b->shared) {
+    if (!b->jslots_host.empty())
+      SYNIM_HIP_TRY(hipMemcpyAsync(b->ws + b->off_jslots, b->jslots_host.data(),
+                                   b->jslots_host.size() * sizeof(int), hipMemcpyHostToDevice, st));
+    SYNIM_HIP_TRY(hipMemcpyAsync(b->ws + b->off_jgroups, b->jgroups_host.data(),
+                                 b->jgroups_host.size() * sizeof(int2), hipMemcpyHostToDevice,
+                                 st));
+  }
   SYNIM_HIP_TRY(hipStreamSynchronize(st));   // the host vectors go out of scope
   return SYNIM_OK;
 }
 
 // Enqueue plans and the stream launch for the pairs of the first n_groups
 // groups (all by default): their records form a prefix of every XCD queue,
-// since the records are dealt group-major; plan jobs follow the group order
-// only when each pair is its own group (the misregistration batches).
+// since the records are dealt group-major, and their plan jobs a prefix of
+// the job table, which is in group order.
 int batch_enqueue(synim_batch* b, hipStream_t st, int n_groups = -1) {
   int np = (int)b->pairs.size();
   int items[8];
@@ -1911,10 +2204,30 @@ int batch_enqueue(synim_batch* b, hipStream_t st, int n_groups = -1) {
       items[x] = acc;
     }
   }
-  int rc = enqueue_plans(PlanJob{}, reinterpret_cast<const PlanJob*>(b->ws + b->off_jobs), np,
-                         b->max_nv, b->max_e, b->max_slots, b->max_tiles, st);
+  const PlanJob* jobs = reinterpret_cast<const PlanJob*>(b->ws + b->off_jobs);
+  int rc = enqueue_plans(PlanJob{}, jobs, np, b->max_nv, b->max_e, b->max_slots, b->max_tiles, st,
+                         !b->shared);
   if (rc != SYNIM_OK) return rc;
   StreamArgs g{};
+  if (b->shared) {
+    int* jstatus = reinterpret_cast<int*>(b->ws + b->off_jstatus);
+    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, jstatus, 16);
+    SYNIM_HIP_TRY(hipGetLastError());
+    if (b->n_jt > 0) {
+      hipLaunchKernelGGL(plan_rows_shared_kernel, dim3((unsigned)b->n_jt), dim3(256), 0, st, jobs,
+                         reinterpret_cast<const int*>(b->ws + b->off_jslots), b->n_jt, b->jNS,
+                         b->var->PW, b->jBHmax, b->var->cap_floats(),
+                         reinterpret_cast<int2*>(b->ws + b->off_jrows),
+                         reinterpret_cast<int4*>(b->ws + b->off_jinfo), jstatus);
+      SYNIM_HIP_TRY(hipGetLastError());
+    }
+    g.jslots = reinterpret_cast<const int*>(b->ws + b->off_jslots);
+    g.jinfo = reinterpret_cast<const int4*>(b->ws + b->off_jinfo);
+    g.jrows = reinterpret_cast<const int2*>(b->ws + b->off_jrows);
+    g.jgroups = reinterpret_cast<const int2*>(b->ws + b->off_jgroups);
+    g.jNS = b->jNS;
+    g.jBHmax = b->jBHmax;
+  }
   g.pairs = reinterpret_cast<const PairDesc*>(b->ws + b->off_pairs);
   g.recs = reinterpret_cast<const SuperChunk*>(b->ws + b->off_recs);
   g.groups = reinterpret_cast<const int2*>(b->ws + b->off_groups);
@@ -1927,7 +2240,7 @@ int batch_enqueue(synim_batch* b, hipStream_t st, int n_groups = -1) {
   g.scratch = reinterpret_cast<float*>(b->ws + b->off_scratch);
   hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, g.counters, 8 * b->planes);
   SYNIM_HIP_TRY(hipGetLastError());
-  StreamFn fn = pick_fn(*b->var, b->vec4, false);
+  StreamFn fn = pick_fn(*b->var, b->vec4, false, true);
   hipLaunchKernelGGL(fn, dim3((unsigned)b->G, 1, b->planes), dim3(b->var->BLOCK), 0, st, g);
   SYNIM_HIP_TRY(hipGetLastError());
   return SYNIM_OK;
@@ -1978,6 +2291,29 @@ void batch_fill(synim_batch* b, const synim_wfs* wfs, int n_wfs, const synim_dm*
                    [&](int x, int y) { return b->group[x] < b->group[y]; });
 }
 
+// Shared tiles when some DM group holds several single-plane pairs; the
+// WFS valid lists come to the host for the binning.  Off: the one GPU run of
+// this path ran with the miscompiled batch kernel form described at the
+// stream kernel, faulted, and has not been run since.
+constexpr bool kSharedTiles = false;
+int batch_pick_shared(synim_batch* b) {
+  b->shared = false;
+  if (!kSharedTiles || b->planes != 1) return SYNIM_OK;
+  std::vector<int> per(b->n_groups, 0);
+  for (int gi : b->group) ++per[gi];
+  bool any = false;
+  for (int c : per) any = any || c > 1;
+  if (!any) return SYNIM_OK;
+  b->valid_host.assign(b->wfs.size(), {});
+  for (size_t w = 0; w < b->wfs.size(); ++w) {
+    b->valid_host[w].resize(b->wfs[w].n_valid);
+    SYNIM_HIP_TRY(hipMemcpy(b->valid_host[w].data(), b->wfs[w].valid_idx,
+                            b->wfs[w].n_valid * sizeof(int32_t), hipMemcpyDeviceToHost));
+  }
+  b->shared = true;
+  return SYNIM_OK;
+}
+
 }  // namespace
 }  // namespace synim
 
@@ -1989,6 +2325,8 @@ extern "C" int synim_batch_workspace(const synim_wfs* wfs, int n_wfs, const syni
   if (rc != SYNIM_OK) return rc;
   synim_batch b;
   batch_fill(&b, wfs, n_wfs, dms, n_dm, pairs, n_pairs);
+  rc = batch_pick_shared(&b);
+  if (rc != SYNIM_OK) return rc;
   size_t m = 0;
   for (int r = 0;; ++r) {
     const Variant* v = batch_variant(&b, r);
@@ -2013,8 +2351,9 @@ extern "C" int synim_batch_create(const synim_wfs* wfs, int n_wfs, const synim_d
   batch_fill(b, wfs, n_wfs, dms, n_dm, pairs, n_pairs);
   b->ws = static_cast<char*>(ws);
   b->ws_bytes = ws_bytes;
-  const Variant* v = batch_variant(b, 0);
-  rc = v ? batch_bind(b, *v, st) : SYNIM_E_UNSUPPORTED;
+  rc = batch_pick_shared(b);
+  const Variant* v = rc == SYNIM_OK ? batch_variant(b, 0) : nullptr;
+  rc = rc != SYNIM_OK ? rc : v ? batch_bind(b, *v, st) : SYNIM_E_UNSUPPORTED;
   if (rc == SYNIM_OK && hipHostMalloc(reinterpret_cast<void**>(&b->staging),
                                       n_pairs * sizeof(MapD), hipHostMallocDefault) != hipSuccess)
     rc = SYNIM_E_HIP;
@@ -2042,8 +2381,16 @@ extern "C" int synim_batch_set_maps(synim_batch* b, const synim_affine* maps, vo
   for (int i = 0; i < np; ++i) {
     const double det = maps[i].A[0][0] * maps[i].A[1][1] - maps[i].A[0][1] * maps[i].A[1][0];
     if (!(std::fabs(det) > 1e-12)) return SYNIM_E_PARAM;
-    b->staging[i] = to_map(maps[i]);
   }
+  if (b->shared && !shared_maps_fit(b, maps)) {
+    // a subaperture moved past the margin of its shared tile: re-bin for the
+    // new maps (a captured graph is captured again on the next run)
+    for (int i = 0; i < np; ++i) b->pairs[i].A = maps[i];
+    const int rc = batch_bind(b, *b->var, st);
+    if (rc != SYNIM_OK) return rc;
+    batch_drop_graph(b);
+  }
+  for (int i = 0; i < np; ++i) b->staging[i] = to_map(maps[i]);
   SYNIM_HIP_TRY(hipMemcpyAsync(b->ws + b->off_maps, b->staging, np * sizeof(MapD),
                                hipMemcpyHostToDevice, st));
   SYNIM_HIP_TRY(hipEventRecord(b->staged, st));
@@ -2081,10 +2428,13 @@ extern "C" int synim_batch_run_graph(synim_batch* b, void* stream) {
 extern "C" int synim_batch_status(synim_batch* b, int* host_out, void* stream) {
   if (!b || !host_out) return SYNIM_E_NULL;
   hipStream_t st = (hipStream_t)stream;
-  std::vector<int> s(b->plans.size(), 0);
+  std::vector<int> s(b->plans.size() + 1, 0);
   for (size_t i = 0; i < b->plans.size(); ++i)
     SYNIM_HIP_TRY(hipMemcpyAsync(&s[i], b->plans[i].status(), sizeof(int), hipMemcpyDeviceToHost,
                                  st));
+  if (b->shared)
+    SYNIM_HIP_TRY(hipMemcpyAsync(&s.back(), b->ws + b->off_jstatus, sizeof(int),
+                                 hipMemcpyDeviceToHost, st));
   SYNIM_HIP_TRY(hipStreamSynchronize(st));
   int v = 0;
   for (int x : s) v |= x;
