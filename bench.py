@@ -246,6 +246,9 @@ def main():
                          "(the workload of the fit's kernel trace)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--mcao-only", action="store_true",
+                    help="only run the MCAO batch leg (the workload of its kernel trace) and "
+                         "print its figures")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -260,6 +263,12 @@ def main():
     if args.misreg_replay:
         from paper_2606_07759_amd import learned
         learned.replay_fits()
+        return
+    if args.mcao_only:
+        import paper_2606_07759_amd as synim
+        synim.load()
+        import torch
+        print(json.dumps(mcao_leg(synim, torch.device("cuda:0"))), flush=True)
         return
     if args.gpus != 1:
         print("bench.py measures one GPU: the IM build shards by actuator columns with no "
