@@ -289,11 +289,16 @@ __device__ __forceinline__ void build_tile_rows(int t, int NS, int PW, int BHmax
                                                 int* status) {
   __shared__ int s_ox[1024], s_oy[1024], s_oe[1024];
   __shared__ int s_x0[MAX_TILE_ROWS], s_w[MAX_TILE_ROWS];
+  __shared__ int s_lo[MAX_TILE_ROWS], s_hi[MAX_TILE_ROWS];
   __shared__ int s_ymin, s_ymax;
   const int tid = threadIdx.x;
   if (tid == 0) {
     s_ymin = INT_MAX;
     s_ymax = INT_MIN;
+  }
+  for (int r = tid; r < MAX_TILE_ROWS; r += blockDim.x) {
+    s_lo[r] = INT_MAX;
+    s_hi[r] = INT_MIN;
   }
   __syncthreads();
   for (int s = tid; s < NS; s += blockDim.x) {
@@ -326,16 +331,18 @@ __device__ __forceinline__ void build_tile_rows(int t, int NS, int PW, int BHmax
     }
     return;
   }
-  for (int r = tid; r < bh; r += blockDim.x) {
-    const int y = y0 + r;
-    int lo = INT_MAX, hi = INT_MIN;
-    for (int s = 0; s < NS; ++s) {
-      const int oy = s_oy[s];
-      if (oy != INT_MIN && oy <= y && y < s_oe[s]) {
-        lo = min(lo, s_ox[s]);
-        hi = max(hi, s_ox[s] + PW);
-      }
+  // each slot widens the column span of every row its weights touch
+  for (int s = tid; s < NS; s += blockDim.x) {
+    const int oy = s_oy[s];
+    if (oy == INT_MIN) continue;
+    for (int y = oy; y < s_oe[s]; ++y) {
+      atomicMin(&s_lo[y - y0], s_ox[s]);
+      atomicMax(&s_hi[y - y0], s_ox[s] + PW);
     }
+  }
+  __syncthreads();
+  for (int r = tid; r < bh; r += blockDim.x) {
+    const int lo = s_lo[r], hi = s_hi[r];
     if (lo == INT_MAX) {
       s_x0[r] = 0;
       s_w[r] = 0;
