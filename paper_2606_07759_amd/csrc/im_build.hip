@@ -149,6 +149,9 @@ __device__ __forceinline__ int in_sub(const uint8_t* __restrict__ pupil, int W, 
 // fixed order, every haloed-window sample q whose bilinear cell has this entry
 // as a tap.  Weights layout: [plane][kk][component x|y][PH*PW].  A used entry
 // widens its subaperture's row range in s_lo/s_hi (index kk - kk0).
+// MULTI = false: the IM plane alone (J.n_planes == 1); the derivative maps and
+// their accumulators then take no registers.
+template <bool MULTI>
 __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long gid, int kk0,
                                                   int* s_lo, int* s_hi) {
   const MapD m = J.m_dev ? *J.m_dev : J.m;
@@ -174,12 +177,14 @@ __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long 
   const int xl = max(u * p - 1, (int)ceil(qx - rx)), xh = min(u * p + p, (int)floor(qx + rx));
   const int yl = max(v * p - 1, (int)ceil(qy - ry)), yh = min(v * p + p, (int)floor(qy + ry));
   const int sx0 = u * p, sy0 = v * p;
+  const int n_planes = MULTI ? J.n_planes : 1;
   Map4 dm{};
-  if (J.n_planes > 1) dm = J.dm_dev ? *J.dm_dev : J.dm;
+  if (MULTI && n_planes > 1) dm = J.dm_dev ? *J.dm_dev : J.dm;
 
-  double acc[5][2];
+  constexpr int NP = MULTI ? 5 : 1;
+  double acc[NP][2];
 #pragma unroll
-  for (int j = 0; j < 5; ++j) acc[j][0] = acc[j][1] = 0.0;
+  for (int j = 0; j < NP; ++j) acc[j][0] = acc[j][1] = 0.0;
   for (int y = yl; y <= yh; ++y)
     for (int x = xl; x <= xh; ++x) {
       const int cx = in_sub(J.pupil, W, sx0, sy0, p, x - 1, y) - in_sub(J.pupil, W, sx0, sy0, p, x + 1, y);
@@ -196,28 +201,34 @@ __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long 
       const double w = wx * wy;
       acc[0][0] += cx * w;
       acc[0][1] += cy * w;
-      if (J.n_planes > 1) {
-        // floor-cell gradient of the tap weight w.r.t. the source point
-        const double dwa = (di == 0.0 ? -1.0 : 1.0) * wy;
-        const double dwb = (dj == 0.0 ? -1.0 : 1.0) * wx;
+      if constexpr (MULTI) {
+        if (n_planes > 1) {
+          // floor-cell gradient of the tap weight w.r.t. the source point
+          const double dwa = (di == 0.0 ? -1.0 : 1.0) * wy;
+          const double dwb = (dj == 0.0 ? -1.0 : 1.0) * wx;
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const double dxs = dm.m[j].a00 * x + dm.m[j].a01 * y + dm.m[j].b0;
-          const double dys = dm.m[j].a10 * x + dm.m[j].a11 * y + dm.m[j].b1;
-          const double d = dwa * dxs + dwb * dys;
-          acc[1 + j][0] += cx * d;
-          acc[1 + j][1] += cy * d;
+          for (int j = 0; j < 4; ++j) {
+            const double dxs = dm.m[j].a00 * x + dm.m[j].a01 * y + dm.m[j].b0;
+            const double dys = dm.m[j].a10 * x + dm.m[j].a11 * y + dm.m[j].b1;
+            const double d = dwa * dxs + dwb * dys;
+            acc[1 + j][0] += cx * d;
+            acc[1 + j][1] += cy * d;
+          }
         }
       }
     }
   const double s = J.inv2nk[kk];
   bool used = false;
-  for (int j = 0; j < J.n_planes; ++j) used = used || acc[j][0] != 0.0 || acc[j][1] != 0.0;
+#pragma unroll
+  for (int j = 0; j < NP; ++j)
+    if (j < n_planes) used = used || acc[j][0] != 0.0 || acc[j][1] != 0.0;
   if (used) {
     atomicMin(&s_lo[kk - kk0], r);
     atomicMax(&s_hi[kk - kk0], r + 1);
   }
-  for (int j = 0; j < J.n_planes; ++j) {
+#pragma unroll
+  for (int j = 0; j < NP; ++j) {
+    if (j >= n_planes) break;
     float* w = J.weights + ((size_t)j * J.nv + kk) * 2 * E;
     w[e] = (float)(acc[j][0] * s);
     w[E + e] = (float)(acc[j][1] * s);
@@ -225,8 +236,9 @@ __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long 
 }
 
 // One thread per (valid subaperture, patch entry), PLAN_WEIGHTS_BLOCK per
-// workgroup.
+// workgroup.  MULTI: some job has derivative planes (n_planes > 1).
 constexpr int PLAN_WEIGHTS_BLOCK = 256;
+template <bool MULTI>
 __global__ __launch_bounds__(PLAN_WEIGHTS_BLOCK) void plan_weights_kernel(
     PlanJob one, const PlanJob* __restrict__ jobs) {
   const PlanJob& J = job_of(one, jobs);
@@ -241,7 +253,7 @@ __global__ __launch_bounds__(PLAN_WEIGHTS_BLOCK) void plan_weights_kernel(
   s_lo[threadIdx.x] = INT_MAX;
   s_hi[threadIdx.x] = INT_MIN;
   __syncthreads();
-  if (gid < (long)J.nv * E) plan_weight_entry(J, E, gid, kk0, s_lo, s_hi);
+  if (gid < (long)J.nv * E) plan_weight_entry<MULTI>(J, E, gid, kk0, s_lo, s_hi);
   __syncthreads();
   const int kk = kk0 + threadIdx.x;
   if (kk < J.nv && s_lo[threadIdx.x] != INT_MAX) {
@@ -1420,7 +1432,7 @@ PlanJob make_job(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map
 // tiles = false: origins, row ranges and weights only (the batch's shared
 // tiles replace the per-pair tile tables).
 int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv, int max_e,
-                  int max_slots, int max_tiles, hipStream_t st, bool tiles = true) {
+                  int max_slots, int max_tiles, int planes, hipStream_t st, bool tiles = true) {
   if (jobs_dev) {
     hipLaunchKernelGGL(zero_job_status_kernel, dim3((n + 255) / 256), dim3(256), 0, st, jobs_dev,
                        n);
@@ -1437,10 +1449,11 @@ int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv
                        dim3(PLAN_SUBAPS_BLOCK), 0, st, one, jt);
     SYNIM_HIP_TRY(hipGetLastError());
     const long nthr = (long)max_nv * max_e;
-    hipLaunchKernelGGL(plan_weights_kernel,
-                       dim3((unsigned)((nthr + PLAN_WEIGHTS_BLOCK - 1) / PLAN_WEIGHTS_BLOCK), nj),
-                       dim3(PLAN_WEIGHTS_BLOCK),
-                       0, st, one, jt);
+    const dim3 wgrid((unsigned)((nthr + PLAN_WEIGHTS_BLOCK - 1) / PLAN_WEIGHTS_BLOCK), nj);
+    if (planes > 1)
+      hipLaunchKernelGGL(plan_weights_kernel<true>, wgrid, dim3(PLAN_WEIGHTS_BLOCK), 0, st, one, jt);
+    else
+      hipLaunchKernelGGL(plan_weights_kernel<false>, wgrid, dim3(PLAN_WEIGHTS_BLOCK), 0, st, one, jt);
     SYNIM_HIP_TRY(hipGetLastError());
     if (!tiles) continue;
     hipLaunchKernelGGL(plan_slots_kernel, dim3((unsigned)((max_slots + 255) / 256), nj),
@@ -1455,7 +1468,8 @@ int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv
 int enqueue_plan(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map4& dm, int planes,
                  const Plan& P, hipStream_t st) {
   const PlanJob J = make_job(w, m, m_dev, dm, nullptr, planes, P);
-  return enqueue_plans(J, nullptr, 1, J.nv, J.PH * J.PW, J.n_tiles * J.NSLOT, J.n_tiles, st);
+  return enqueue_plans(J, nullptr, 1, J.nv, J.PH * J.PW, J.n_tiles * J.NSLOT, J.n_tiles,
+                       J.n_planes, st);
 }
 
 // Resident workgroups of a stream kernel on the current device (cached).
@@ -2212,8 +2226,8 @@ int batch_enqueue(synim_batch* b, hipStream_t st, int n_groups = -1) {
     }
   }
   const PlanJob* jobs = reinterpret_cast<const PlanJob*>(b->ws + b->off_jobs);
-  int rc = enqueue_plans(PlanJob{}, jobs, np, b->max_nv, b->max_e, b->max_slots, b->max_tiles, st,
-                         !b->shared);
+  int rc = enqueue_plans(PlanJob{}, jobs, np, b->max_nv, b->max_e, b->max_slots, b->max_tiles,
+                         b->planes, st, !b->shared);
   if (rc != SYNIM_OK) return rc;
   StreamArgs g{};
   if (b->shared) {
