@@ -75,8 +75,13 @@ struct PlanJob {
   int* status;
 };
 
+// The job of this workgroup.  TABLE = false: the one job passed by value, read
+// from the kernel arguments (scalar loads); TABLE = true: row blockIdx.y of a
+// device job table.
+template <bool TABLE>
 __device__ __forceinline__ const PlanJob& job_of(const PlanJob& one, const PlanJob* jobs) {
-  return jobs ? jobs[blockIdx.y] : one;
+  if constexpr (TABLE) return jobs[blockIdx.y];
+  else return one;
 }
 
 // Origin (patch corner) and 1/(2 n_k) of each valid subaperture: one wave
@@ -91,9 +96,10 @@ __device__ __forceinline__ double wave_max(double v) {
   for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
+template <bool TABLE>
 __global__ __launch_bounds__(PLAN_SUBAPS_BLOCK) void plan_subaps_kernel(
     PlanJob one, const PlanJob* __restrict__ jobs) {
-  const PlanJob& J = job_of(one, jobs);
+  const PlanJob& J = job_of<TABLE>(one, jobs);
   const int kk = (int)((blockIdx.x * PLAN_SUBAPS_BLOCK + threadIdx.x) >> 6);
   const int lane = threadIdx.x & 63;
   if (kk >= J.nv) return;   // whole waves
@@ -238,10 +244,10 @@ __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long 
 // One thread per (valid subaperture, patch entry), PLAN_WEIGHTS_BLOCK per
 // workgroup.  MULTI: some job has derivative planes (n_planes > 1).
 constexpr int PLAN_WEIGHTS_BLOCK = 256;
-template <bool MULTI>
+template <bool MULTI, bool TABLE>
 __global__ __launch_bounds__(PLAN_WEIGHTS_BLOCK) void plan_weights_kernel(
     PlanJob one, const PlanJob* __restrict__ jobs) {
-  const PlanJob& J = job_of(one, jobs);
+  const PlanJob& J = job_of<TABLE>(one, jobs);
   const int E = J.PH * J.PW;
   const long g0 = (long)blockIdx.x * PLAN_WEIGHTS_BLOCK;
   const long gid = g0 + threadIdx.x;
@@ -274,8 +280,9 @@ __device__ int find_valid(const int32_t* __restrict__ valid, int nv, int k) {
 }
 
 // One thread per (tile, slot): which valid subaperture (if any) the slot holds.
+template <bool TABLE>
 __global__ void plan_slots_kernel(PlanJob one, const PlanJob* __restrict__ jobs) {
-  const PlanJob& J = job_of(one, jobs);
+  const PlanJob& J = job_of<TABLE>(one, jobs);
   const int NS = J.TX * J.TY;
   const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
   if (gid >= (long)J.n_tiles * NS) return;
@@ -398,9 +405,10 @@ __device__ __forceinline__ void build_tile_rows(int t, int NS, int PW, int BHmax
   }
 }
 
+template <bool TABLE>
 __global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
                                                         const PlanJob* __restrict__ jobs) {
-  const PlanJob& J = job_of(one, jobs);
+  const PlanJob& J = job_of<TABLE>(one, jobs);
   const int t = blockIdx.x;
   if (t >= J.n_tiles) return;
   const int NS = J.NSLOT;
@@ -1427,6 +1435,37 @@ PlanJob make_job(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map
   return J;
 }
 
+template <bool TABLE>
+int enqueue_plan_kernels(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv,
+                         int max_e, int max_slots, int max_tiles, int planes, hipStream_t st,
+                         bool tiles) {
+  for (int j0 = 0; j0 < n; j0 += 65535) {
+    const int nj = std::min(65535, n - j0);
+    const PlanJob* jt = TABLE ? jobs_dev + j0 : nullptr;
+    hipLaunchKernelGGL(plan_subaps_kernel<TABLE>,
+                       dim3((unsigned)(((long)max_nv * 64 + PLAN_SUBAPS_BLOCK - 1) / PLAN_SUBAPS_BLOCK),
+                            nj),
+                       dim3(PLAN_SUBAPS_BLOCK), 0, st, one, jt);
+    SYNIM_HIP_TRY(hipGetLastError());
+    const long nthr = (long)max_nv * max_e;
+    const dim3 wgrid((unsigned)((nthr + PLAN_WEIGHTS_BLOCK - 1) / PLAN_WEIGHTS_BLOCK), nj);
+    if (planes > 1)
+      hipLaunchKernelGGL((plan_weights_kernel<true, TABLE>), wgrid, dim3(PLAN_WEIGHTS_BLOCK), 0,
+                         st, one, jt);
+    else
+      hipLaunchKernelGGL((plan_weights_kernel<false, TABLE>), wgrid, dim3(PLAN_WEIGHTS_BLOCK), 0,
+                         st, one, jt);
+    SYNIM_HIP_TRY(hipGetLastError());
+    if (!tiles) continue;
+    hipLaunchKernelGGL(plan_slots_kernel<TABLE>, dim3((unsigned)((max_slots + 255) / 256), nj),
+                       dim3(256), 0, st, one, jt);
+    SYNIM_HIP_TRY(hipGetLastError());
+    hipLaunchKernelGGL(plan_rows_kernel<TABLE>, dim3(max_tiles, nj), dim3(256), 0, st, one, jt);
+    SYNIM_HIP_TRY(hipGetLastError());
+  }
+  return SYNIM_OK;
+}
+
 // Enqueue the plan kernels for `n` jobs: one job by value (jobs_dev null) or
 // a device table of n jobs (maxima give the grid extents).
 // tiles = false: origins, row ranges and weights only (the batch's shared
@@ -1440,29 +1479,11 @@ int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv
     hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, one.status, 16);
   }
   SYNIM_HIP_TRY(hipGetLastError());
-  for (int j0 = 0; j0 < n; j0 += 65535) {
-    const int nj = std::min(65535, n - j0);
-    const PlanJob* jt = jobs_dev ? jobs_dev + j0 : nullptr;
-    hipLaunchKernelGGL(plan_subaps_kernel,
-                       dim3((unsigned)(((long)max_nv * 64 + PLAN_SUBAPS_BLOCK - 1) / PLAN_SUBAPS_BLOCK),
-                            nj),
-                       dim3(PLAN_SUBAPS_BLOCK), 0, st, one, jt);
-    SYNIM_HIP_TRY(hipGetLastError());
-    const long nthr = (long)max_nv * max_e;
-    const dim3 wgrid((unsigned)((nthr + PLAN_WEIGHTS_BLOCK - 1) / PLAN_WEIGHTS_BLOCK), nj);
-    if (planes > 1)
-      hipLaunchKernelGGL(plan_weights_kernel<true>, wgrid, dim3(PLAN_WEIGHTS_BLOCK), 0, st, one, jt);
-    else
-      hipLaunchKernelGGL(plan_weights_kernel<false>, wgrid, dim3(PLAN_WEIGHTS_BLOCK), 0, st, one, jt);
-    SYNIM_HIP_TRY(hipGetLastError());
-    if (!tiles) continue;
-    hipLaunchKernelGGL(plan_slots_kernel, dim3((unsigned)((max_slots + 255) / 256), nj),
-                       dim3(256), 0, st, one, jt);
-    SYNIM_HIP_TRY(hipGetLastError());
-    hipLaunchKernelGGL(plan_rows_kernel, dim3(max_tiles, nj), dim3(256), 0, st, one, jt);
-    SYNIM_HIP_TRY(hipGetLastError());
-  }
-  return SYNIM_OK;
+  if (jobs_dev)
+    return enqueue_plan_kernels<true>(one, jobs_dev, n, max_nv, max_e, max_slots, max_tiles,
+                                      planes, st, tiles);
+  return enqueue_plan_kernels<false>(one, nullptr, 1, max_nv, max_e, max_slots, max_tiles,
+                                     planes, st, tiles);
 }
 
 int enqueue_plan(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map4& dm, int planes,
