@@ -17,9 +17,9 @@
 //   plan_weights  one thread per patch entry gathers every (q, tap) that lands
 //                 on it; the Jacobian planes use d w_tap / d theta_j from the
 //                 floor-cell bilinear gradient and the derivative maps;
-//   plan_slots    groups subapertures into tiles;
-//   plan_rows     lists, for every tile, the IF rows its patches touch, each
-//                 trimmed to the columns they cover, packed for staging.
+//   plan_rows     groups subapertures into tiles and lists, for every tile,
+//                 the IF rows its patches touch, each trimmed to the columns
+//                 they cover, packed for staging.
 // Stream (FP32, the hot loop): a persistent kernel hands out (actuator chunk,
 // tile) items from per-XCD queues.  For an item the workgroup loads the tile's
 // weights into registers, then streams every actuator's packed tile rows from
@@ -279,21 +279,6 @@ __device__ int find_valid(const int32_t* __restrict__ valid, int nv, int k) {
   return -1;
 }
 
-// One thread per (tile, slot): which valid subaperture (if any) the slot holds.
-template <bool TABLE>
-__global__ void plan_slots_kernel(PlanJob one, const PlanJob* __restrict__ jobs) {
-  const PlanJob& J = job_of<TABLE>(one, jobs);
-  const int NS = J.TX * J.TY;
-  const long gid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid >= (long)J.n_tiles * NS) return;
-  const int t = (int)(gid / NS), s = (int)(gid - (long)t * NS);
-  const int tu = t % J.n_tiles_x, tv = t / J.n_tiles_x;
-  const int u = tu * J.TX + s % J.TX, v = tv * J.TY + s / J.TX;
-  int kk = -1;
-  if (u < J.n_sub_x && v < J.n_sub_y) kk = find_valid(J.valid, J.nv, v * J.n_sub_x + u);
-  J.slot_kk[gid] = kk;
-}
-
 // One workgroup per tile: the IF rows its patches touch, each trimmed to the
 // column interval those patches cover (aligned to 4 floats), packed one after
 // the other.  tile_info[t] = (y0, rows, packed floats, 0), rows = 0 for an empty
@@ -415,7 +400,13 @@ __global__ __launch_bounds__(256) void plan_rows_kernel(PlanJob one,
   build_tile_rows(
       t, NS, J.PW, J.BHmax, J.cap_floats,
       [&](int s, int2& o, int2& hr) {
-        const int kk = J.slot_kk[(size_t)t * NS + s];
+        // the valid subaperture (if any) slot s of tile t holds, kept for the
+        // stream kernel
+        const int u = (t % J.n_tiles_x) * J.TX + s % J.TX;
+        const int v = (t / J.n_tiles_x) * J.TY + s / J.TX;
+        int kk = -1;
+        if (u < J.n_sub_x && v < J.n_sub_y) kk = find_valid(J.valid, J.nv, v * J.n_sub_x + u);
+        J.slot_kk[(size_t)t * NS + s] = kk;
         o = make_int2(0, 0);
         hr = make_int2(0, 0);
         if (kk >= 0) {
@@ -1389,7 +1380,6 @@ int build_plan_with(const synim_wfs& w, const synim_affine& A, const synim_affin
   if (!ws) return SYNIM_E_WORKSPACE;
   if (ws_bytes < P->L.total) return SYNIM_E_WORKSPACE;
   P->ws = static_cast<char*>(ws);
-  const Dims& d = P->d;
   const MapD m = to_map(A);
   const double det = m.a00 * m.a11 - m.a01 * m.a10;
   if (!(std::fabs(det) > 1e-12)) return SYNIM_E_PARAM;
@@ -1437,7 +1427,7 @@ PlanJob make_job(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map
 
 template <bool TABLE>
 int enqueue_plan_kernels(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv,
-                         int max_e, int max_slots, int max_tiles, int planes, hipStream_t st,
+                         int max_e, int max_tiles, int planes, hipStream_t st,
                          bool tiles) {
   for (int j0 = 0; j0 < n; j0 += 65535) {
     const int nj = std::min(65535, n - j0);
@@ -1457,9 +1447,6 @@ int enqueue_plan_kernels(const PlanJob& one, const PlanJob* jobs_dev, int n, int
                          st, one, jt);
     SYNIM_HIP_TRY(hipGetLastError());
     if (!tiles) continue;
-    hipLaunchKernelGGL(plan_slots_kernel<TABLE>, dim3((unsigned)((max_slots + 255) / 256), nj),
-                       dim3(256), 0, st, one, jt);
-    SYNIM_HIP_TRY(hipGetLastError());
     hipLaunchKernelGGL(plan_rows_kernel<TABLE>, dim3(max_tiles, nj), dim3(256), 0, st, one, jt);
     SYNIM_HIP_TRY(hipGetLastError());
   }
@@ -1471,7 +1458,7 @@ int enqueue_plan_kernels(const PlanJob& one, const PlanJob* jobs_dev, int n, int
 // tiles = false: origins, row ranges and weights only (the batch's shared
 // tiles replace the per-pair tile tables).
 int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv, int max_e,
-                  int max_slots, int max_tiles, int planes, hipStream_t st, bool tiles = true) {
+                  int max_tiles, int planes, hipStream_t st, bool tiles = true) {
   if (jobs_dev) {
     hipLaunchKernelGGL(zero_job_status_kernel, dim3((n + 255) / 256), dim3(256), 0, st, jobs_dev,
                        n);
@@ -1480,17 +1467,16 @@ int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv
   }
   SYNIM_HIP_TRY(hipGetLastError());
   if (jobs_dev)
-    return enqueue_plan_kernels<true>(one, jobs_dev, n, max_nv, max_e, max_slots, max_tiles,
+    return enqueue_plan_kernels<true>(one, jobs_dev, n, max_nv, max_e, max_tiles,
                                       planes, st, tiles);
-  return enqueue_plan_kernels<false>(one, nullptr, 1, max_nv, max_e, max_slots, max_tiles,
+  return enqueue_plan_kernels<false>(one, nullptr, 1, max_nv, max_e, max_tiles,
                                      planes, st, tiles);
 }
 
 int enqueue_plan(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map4& dm, int planes,
                  const Plan& P, hipStream_t st) {
   const PlanJob J = make_job(w, m, m_dev, dm, nullptr, planes, P);
-  return enqueue_plans(J, nullptr, 1, J.nv, J.PH * J.PW, J.n_tiles * J.NSLOT, J.n_tiles,
-                       J.n_planes, st);
+  return enqueue_plans(J, nullptr, 1, J.nv, J.PH * J.PW, J.n_tiles, J.n_planes, st);
 }
 
 // Resident workgroups of a stream kernel on the current device (cached).
@@ -1863,7 +1849,7 @@ struct synim_batch {
   size_t ws_bytes = 0;
   size_t off_maps = 0, off_pairs = 0, off_recs = 0, off_groups = 0, off_ctr = 0, off_scratch = 0;
   size_t off_jobs = 0, off_dmaps = 0;
-  int max_nv = 0, max_e = 0, max_slots = 0, max_tiles = 0;
+  int max_nv = 0, max_e = 0, max_tiles = 0;
   int n_recs = 0;
   int rec_off[8] = {}, rec_cnt[8] = {}, xcd_items[8] = {};
   std::vector<SuperChunk> recs_host;   // to count the items of the first groups
@@ -2189,7 +2175,7 @@ int batch_bind(synim_batch* b, const Variant& v, hipStream_t st) {
   b->recs_host = recs;
   std::vector<PlanJob> jobs(np);
   const MapD* maps_dev = reinterpret_cast<const MapD*>(b->ws + b->off_maps);
-  b->max_nv = b->max_e = b->max_slots = b->max_tiles = 0;
+  b->max_nv = b->max_e = b->max_tiles = 0;
   // jobs in group order (the order of the pair table): shared-tile slots and
   // the group prefixes of batch_enqueue index them that way
   for (int pos = 0; pos < np; ++pos) {
@@ -2201,7 +2187,6 @@ int batch_bind(synim_batch* b, const Variant& v, hipStream_t st) {
                          b->planes, b->plans[i]);
     b->max_nv = std::max(b->max_nv, jobs[pos].nv);
     b->max_e = std::max(b->max_e, jobs[pos].PH * jobs[pos].PW);
-    b->max_slots = std::max(b->max_slots, jobs[pos].n_tiles * jobs[pos].NSLOT);
     b->max_tiles = std::max(b->max_tiles, jobs[pos].n_tiles);
   }
   SYNIM_HIP_TRY(hipMemcpyAsync(b->ws + b->off_jobs, jobs.data(), np * sizeof(PlanJob),
@@ -2247,7 +2232,7 @@ int batch_enqueue(synim_batch* b, hipStream_t st, int n_groups = -1) {
     }
   }
   const PlanJob* jobs = reinterpret_cast<const PlanJob*>(b->ws + b->off_jobs);
-  int rc = enqueue_plans(PlanJob{}, jobs, np, b->max_nv, b->max_e, b->max_slots, b->max_tiles,
+  int rc = enqueue_plans(PlanJob{}, jobs, np, b->max_nv, b->max_e, b->max_tiles,
                          b->planes, st, !b->shared);
   if (rc != SYNIM_OK) return rc;
   StreamArgs g{};
