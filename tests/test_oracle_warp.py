@@ -134,3 +134,100 @@ def test_derivative_maps_match_finite_differences_of_the_map():
         fd = ((Ap @ po + bp[:, None]) - (Am @ po + bm[:, None])) / (2 * h)
         an = dm[j][0] @ po + dm[j][1][:, None]
         assert np.max(np.abs(fd - an)) < 1e-6 * max(1.0, np.abs(an).max())
+
+
+# --- WFS side of the composite chain (Sec. 2.1: the WFS transform, anamorphosis
+# included, is multiplied into the same matrix as the DM and the LGS perspective).
+# Each pin below is a point or a permutation worked out by hand, not a re-evaluation
+# of the product.
+
+def _ps(g, po, H_in=512, W_in=512, H_out=476, W_out=476):
+    A, b = geometry.inverse_from_geometry(g, H_in, W_in, H_out, W_out)
+    return A @ np.asarray(po, dtype=np.float64) + b
+
+
+def test_wfs_rotation_quarter_turn_point():
+    # WFS pixel (100, 300) on the 476 grid is (-137.5, 62.5) from its centre 237.5.
+    # The forward map turns DM offsets by +90 deg, (x, y) -> (-y, x); undoing it sends
+    # (-137.5, 62.5) to (62.5, 137.5), i.e. IF pixel 255.5 + (62.5, 137.5).
+    g = wl.Geometry(wfs_rot=math.pi / 2)
+    assert np.max(np.abs(_ps(g, (100.0, 300.0)) - np.array([318.0, 393.0]))) < 1e-12
+
+
+def test_wfs_rotation_quarter_turn_is_exact_permutation():
+    # same-size grids: a +90 deg WFS clocking permutes pixels exactly as rot90(in, -1)
+    F = rng_stack(2, 40, 40, seed=5)
+    A, b = geometry.inverse_from_geometry(wl.Geometry(wfs_rot=math.pi / 2), 40, 40, 40, 40)
+    out = warp.warp(F, A, b, 40, 40, halo=0)
+    assert np.array_equal(out, np.rot90(F, -1, axes=(1, 2)).astype(np.float64))
+
+
+def test_wfs_anamorphic_magnification_point():
+    # forward scales x offsets by 1.05 and y offsets by 0.97 (WFS axes), so the
+    # offset (-137.5, 62.5) comes from (-130.952380952381, 64.43298969072166)
+    g = wl.Geometry(wfs_mag_x=1.05, wfs_mag_y=0.97)
+    expect = 255.5 + np.array([-130.95238095238095, 64.43298969072165])
+    assert np.max(np.abs(_ps(g, (100.0, 300.0)) - expect)) < 1e-11
+
+
+def test_wfs_anamorphic_half_scale_is_exact_decimation():
+    # WFS x magnification 0.5 on an 81-wide IF grid and a 41-wide WFS grid (centres
+    # 40 and 20): x_s = 40 + (x_o - 20) / 0.5 = 2 x_o, y unchanged: out = F[:, :, ::2]
+    F = rng_stack(2, 41, 81, seed=6)
+    A, b = geometry.inverse_from_geometry(wl.Geometry(wfs_mag_x=0.5), 41, 81, 41, 41)
+    out = warp.warp(F, A, b, 41, 41, halo=0)
+    assert np.array_equal(out, F[:, :, 0::2].astype(np.float64))
+
+
+@pytest.mark.parametrize("s", [(3, -2), (-5, 7)])
+def test_wfs_shift_is_exact_translation(s):
+    # a WFS shift moves the image by exactly that many WFS pixels: p_s = p_o + 8 - s
+    F = rng_stack(2, 96, 96, seed=7)
+    A, b = geometry.inverse_from_geometry(wl.Geometry(wfs_shift_x=s[0], wfs_shift_y=s[1]),
+                                          96, 96, 80, 80)
+    out = warp.warp(F, A, b, 80, 80, halo=1)
+    r0, c0 = 7 - s[1], 7 - s[0]
+    assert np.array_equal(out, F[:, r0:r0 + 82, c0:c0 + 82].astype(np.float64))
+
+
+def test_wfs_rotation_then_anamorphosis_order():
+    # forward WFS part = diag(mx, my) R(rot): the clocking turns the footprint first and
+    # the anamorphosis scales along the WFS's own axes.  With rot = 90 deg, mx = 1.25,
+    # my = 0.8: undo diag -> (-137.5/1.25, 62.5/0.8) = (-110, 78.125); undo R(+90) ->
+    # (78.125, 110).  (The other order would give (50, 171.875).)
+    g = wl.Geometry(wfs_rot=math.pi / 2, wfs_mag_x=1.25, wfs_mag_y=0.8)
+    expect = 255.5 + np.array([78.125, 110.0])
+    assert np.max(np.abs(_ps(g, (100.0, 300.0)) - expect)) < 1e-12
+
+
+def test_chain_order_dm_then_footprint_then_wfs():
+    # cone 0.8, footprint (10, -4) DM px, WFS clocking +90 deg, documented order
+    # DM placement -> LGS footprint -> WFS.  Undo the WFS: (-137.5, 62.5) -> (62.5, 137.5);
+    # undo the footprint: 0.8 * (62.5, 137.5) + (10, -4) = (60, 106); IF pixel
+    # 255.5 + (60, 106).  (Footprint applied after the clocking would give (46, 100).)
+    g = wl.Geometry(cone_scale=0.8, footprint_x=10.0, footprint_y=-4.0, wfs_rot=math.pi / 2)
+    expect = np.array([315.5, 361.5])
+    assert np.max(np.abs(_ps(g, (100.0, 300.0)) - expect)) < 1e-12
+
+
+def test_chain_full_worked_point():
+    # every stage at once, worked by hand on WFS offset w = (-137.5, 62.5):
+    #   undo WFS shift (2, -1):          (-139.5, 63.5)
+    #   undo diag(1.25, 0.8):            (-111.6, 79.375)
+    #   undo R(+90):  (x, y) -> (y, -x): (79.375, 111.6)
+    #   undo footprint, cone 0.8:        0.8*(79.375, 111.6) + (10, -4) = (73.5, 85.28)
+    #   undo DM shift (1, 2):            (72.5, 83.28)
+    #   undo DM mag 2 and R(+90):        (x, y)/2 -> (y, -x): (41.64, -36.25)
+    #   IF pixel:                        255.5 + (41.64, -36.25) = (297.14, 219.25)
+    g = wl.Geometry(dm_shift_x=1.0, dm_shift_y=2.0, dm_rot=math.pi / 2, dm_mag=2.0,
+                    cone_scale=0.8, footprint_x=10.0, footprint_y=-4.0,
+                    wfs_shift_x=2.0, wfs_shift_y=-1.0, wfs_rot=math.pi / 2,
+                    wfs_mag_x=1.25, wfs_mag_y=0.8)
+    assert np.max(np.abs(_ps(g, (100.0, 300.0)) - np.array([297.14, 219.25]))) < 1e-11
+
+
+def test_kappa_scales_wfs_offsets_into_dm_pixels():
+    # kappa DM pixels per WFS pixel: with kappa = 2 and nothing else, a WFS offset w maps
+    # to the DM offset 2 w.  WFS pixel (100, 300) on 476 -> 255.5 + (-275, 125).
+    g = wl.Geometry(kappa=2.0)
+    assert np.max(np.abs(_ps(g, (100.0, 300.0)) - np.array([-19.5, 380.5]))) < 1e-12
