@@ -1721,9 +1721,11 @@ void batch_fill(synim_batch* b, const synim_wfs* wfs, int n_wfs, const synim_dm*
 }
 
 // Shared tiles when some DM group holds several single-plane pairs; the
-// WFS valid lists come to the host for the binning.  Off: the one GPU run of
-// this path ran with the miscompiled batch kernel form described at the
-// stream kernel, faulted, and has not been run since.
+// WFS valid lists come to the host for the binning.  Off: its one GPU run gave
+// wrong values and a memory fault.  That run's DMA instructions read their
+// buffer resource one wait state after the v_readfirstlane that wrote it (5
+// are needed), so a DMA could stream from a stale address; the DMA padding in
+// the stream kernel removes that hazard.
 constexpr bool kSharedTiles = false;
 int batch_pick_shared(synim_batch* b) {
   b->shared = false;

@@ -122,11 +122,18 @@ __device__ __forceinline__ void compiler_fence() { asm volatile("" ::: "memory")
 // (its conservative merge at the pipeline loop head drained every DMA in
 // flight there).  Completion is the pipeline's explicit vmcnt waits alone.
 //
-// An LDS DMA reads M0 (its LDS destination) one cycle after issue, so a
-// scalar write of M0 right before it needs one wait state in between, or the
-// DMA may take the previous M0 and land somewhere else in LDS.  The compiler
-// pads its own LDS-DMA instructions with an s_nop for this; it cannot see into
-// inline assembly, so each DMA below opens with that s_nop itself.
+// Two hazards of gfx9 sit between a DMA and the scalar registers it reads,
+// and the compiler pads neither around inline assembly (it does around its own
+// buffer loads):
+//  * a vector-memory instruction that reads an SGPR written by a VALU
+//    instruction (here the v_readfirstlane that builds the buffer resource)
+//    needs 5 wait states in between, or it may read the SGPR's previous value:
+//    the DMA then streams from a stale base address (another actuator's plane,
+//    or no valid address at all) or with a stale record count;
+//  * an LDS DMA reads M0 (its LDS destination) one cycle after issue, so a
+//    scalar write of M0 right before it needs one wait state.
+// Each DMA below therefore opens with s_nop 4 (5 wait states), which covers
+// both whatever the compiler schedules right before the asm block.
 template <int BLOCK, int NJ, int VW>
 __device__ __forceinline__ void stage_issue(const float* plane_ptr, int plane_bytes,
                                             const unsigned* voff, float4* buf, int wave) {
@@ -136,11 +143,11 @@ __device__ __forceinline__ void stage_issue(const float* plane_ptr, int plane_by
     const unsigned m0 =
         lds_addr(reinterpret_cast<float*>(buf) + (size_t)(BLOCK * j + 64 * wave) * VW);
     if constexpr (VW == 4)
-      asm volatile("s_nop 0\n\tbuffer_load_dwordx4 %0, %1, 0 offen lds" ::"v"(voff[j]), "s"(r),
+      asm volatile("s_nop 4\n\tbuffer_load_dwordx4 %0, %1, 0 offen lds" ::"v"(voff[j]), "s"(r),
                    "{m0}"(m0)
                    : "memory");
     else
-      asm volatile("s_nop 0\n\tbuffer_load_dword %0, %1, 0 offen lds" ::"v"(voff[j]), "s"(r),
+      asm volatile("s_nop 4\n\tbuffer_load_dword %0, %1, 0 offen lds" ::"v"(voff[j]), "s"(r),
                    "{m0}"(m0)
                    : "memory");
   }
@@ -195,7 +202,7 @@ constexpr int SYNC_STRIDE = 32;       // ints between the counters (own 128-byte
 __device__ __forceinline__ void snapshot_issue(const int* ctr, int* lds_dst) {
   const u32x4 r = buffer_rsrc(ctr, 4u);
   const unsigned m0 = lds_addr(lds_dst);
-  asm volatile("s_nop 0\n\tbuffer_load_dword %0, %1, 0 offen sc1 lds" ::"v"(0u), "s"(r),
+  asm volatile("s_nop 4\n\tbuffer_load_dword %0, %1, 0 offen sc1 lds" ::"v"(0u), "s"(r),
                "{m0}"(m0)
                : "memory");
 }
@@ -229,10 +236,11 @@ constexpr int stream_waves_per_simd(int block, int nj, int vw, int nst) {
 
 // BATCH = false: the single-pair launches, with every batch path compiled out.
 // BATCH = true: the batched launches; that instantiation keeps the single-pair
-// paths too and picks by g.pairs at run time.  (Compiled with the batch
-// decision fixed instead, the batch kernel gave wrong values for some
-// actuators from run to run; the cause was not found, so that form is not
-// used.)
+// paths too and picks by g.pairs at run time.  (A form with the batch decision
+// fixed at compile time once gave wrong values for some actuators from run to
+// run.  Its DMA read buffer-resource SGPRs that a v_readfirstlane had written
+// one wait state earlier, where 5 are needed; the DMA padding above removes
+// that hazard from every form.)
 template <int BLOCK, int LPS, int RPL, int PW, int NJ, int VW, int NST, int PACK, bool VJP,
           bool BATCH>
 __global__ __launch_bounds__(BLOCK, VW == 4 ? stream_waves_per_simd(BLOCK, NJ, VW, NST) : 1) void
