@@ -67,3 +67,29 @@ def min_cell_edge_distance(A, b, H: int, W: int) -> float:
     dx = np.abs(xs_s - np.round(xs_s))
     dy = np.abs(ys_s - np.round(ys_s))
     return float(min(dx.min(), dy.min()))
+
+
+def oob_count(A, b, pupil, p: int, valid, H_in: int, W_in: int) -> int:
+    """Out-of-grid samples of one IF column (zero-filled by the warp, Sec. 2.1 with the
+    zero-fill reading of the interpolation outside the IF grid).
+
+    Counted per valid subaperture k: the haloed samples q whose central-difference
+    coefficient in k is non-zero (c_x = [q-e_x in k, P=1] - [q+e_x in k, P=1], c_y
+    likewise) and whose source point A q + b lies outside [0, W_in-1] x [0, H_in-1].
+    A sample read by two subapertures counts twice.
+    """
+    H, W = pupil.shape
+    n_sub_x = W // p
+    xs_s, ys_s = _warp.source_coords(A, b, H, W, 1)
+    out = (xs_s < 0) | (xs_s > W_in - 1) | (ys_s < 0) | (ys_s > H_in - 1)
+    total = 0
+    for k in np.asarray(valid).tolist():
+        v, u = divmod(int(k), n_sub_x)
+        m = np.zeros((H + 4, W + 4), np.int64)      # P=1 pixels of k, padded by 2
+        m[v * p + 2:(v + 1) * p + 2, u * p + 2:(u + 1) * p + 2] = \
+            pupil[v * p:(v + 1) * p, u * p:(u + 1) * p] > 0
+        # haloed sample (y, x) in [-1, H] x [-1, W] sits at m[y + 2, x + 2]
+        cx = m[1:-1, :-2] - m[1:-1, 2:]
+        cy = m[:-2, 1:-1] - m[2:, 1:-1]
+        total += int(np.count_nonzero(((cx != 0) | (cy != 0)) & out))
+    return total

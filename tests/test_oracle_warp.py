@@ -231,3 +231,36 @@ def test_kappa_scales_wfs_offsets_into_dm_pixels():
     # to the DM offset 2 w.  WFS pixel (100, 300) on 476 -> 255.5 + (-275, 125).
     g = wl.Geometry(kappa=2.0)
     assert np.max(np.abs(_ps(g, (100.0, 300.0)) - np.array([-19.5, 380.5]))) < 1e-12
+
+
+def test_oob_count_single_subaperture_by_hand():
+    # one 4x4 subaperture, full pupil, identity map onto a 4x4 IF grid: the central
+    # differences read columns {-1, 0, 3, 4} of rows 0..3 (c_x) and rows {-1, 0, 3, 4} of
+    # columns 0..3 (c_y), 28 samples; the 16 in column -1 or 4, or in row -1 or 4, lie
+    # outside the IF grid.
+    from oracle import im as oim
+    pupil = np.ones((4, 4), np.uint8)
+    A, b = geometry.inverse_from_misreg((0, 0, 0, 1), 4, 4, 4, 4)
+    assert oim.oob_count(A, b, pupil, 4, [0], 4, 4) == 16
+    # on a 6x6 IF grid the same samples all lie inside (centred: source = sample + 1)
+    A, b = geometry.inverse_from_misreg((0, 0, 0, 1), 6, 6, 4, 4)
+    assert oim.oob_count(A, b, pupil, 4, [0], 6, 6) == 0
+    # shifted one pixel right (t_x = 1): source x = sample x, so column -1 (4 samples) is
+    # outside; columns 0..4 and rows -1..4 map to 0..4 and 0..5: inside
+    A, b = geometry.inverse_from_misreg((1, 0, 0, 1), 6, 6, 4, 4)
+    assert oim.oob_count(A, b, pupil, 4, [0], 6, 6) == 4
+
+
+def test_oob_count_matches_warp_zero_fill():
+    # every sample the count names is one the warp zero-fills: with a constant IF of 1,
+    # the warped value at those samples is exactly 0 (inside: 1, or a partial edge cell)
+    from oracle import im as oim
+    pupil = wl.pupil_mask(40, 40.0)
+    valid = wl.valid_subapertures(pupil, 5)
+    A, b = geometry.inverse_from_misreg((9.5, -7.25, math.radians(2.0), 0.95), 50, 50, 40, 40)
+    n = oim.oob_count(A, b, pupil, 5, valid, 50, 50)
+    assert n > 0
+    xs, ys = warp.source_coords(A, b, 40, 40, 1)
+    phi = warp.warp(np.ones((1, 50, 50), np.float32), A, b, 40, 40, halo=1)[0]
+    far = (xs < -1) | (xs > 50) | (ys < -1) | (ys > 50)
+    assert np.all(phi[far] == 0.0)
