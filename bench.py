@@ -302,7 +302,7 @@ def main():
     chosen = synim.im_config(wfs, A)
     log(f"chosen {chosen} ({min(tune_ms):.3f} ms best of {len(tune_ms)})")
     for _ in range(args.warmup):
-        synim.im_plan(wfs, A, ws=ws)
+        synim.im_plan(wfs, A, ws=ws, grid=(512, 512))
         synim.im_apply(Fd, A, wfs, ws, out=out)
     torch.cuda.synchronize()
     if synim.plan_status(ws) != 0:
@@ -314,7 +314,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
-        synim.im_plan(wfs, A, ws=ws)
+        synim.im_plan(wfs, A, ws=ws, grid=(512, 512))
         ev[k][0].record()
         synim.im_apply(Fd, A, wfs, ws, out=out)
         ev[k][1].record()

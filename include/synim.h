@@ -15,7 +15,11 @@
  *               grid of n pixels has its centre at (n-1)/2.
  * Inverse map   synim_affine holds p_s = A p_o + b: WFS (output) pixel ->
  *               IF (source) pixel, x first.  IF samples outside the IF grid
- *               are zero.
+ *               are zero (the paper leaves this open; zero fill is the
+ *               reading taken).  The fused builds count the samples the
+ *               slopes read whose source point leaves the grid; the strict
+ *               check synim_plan_oob / synim_batch_oob returns SYNIM_E_OOB
+ *               when that count is non-zero.
  * Subapertures  the WFS grid is (n_sub_y*p) x (n_sub_x*p) pixels; subaperture
  *               (u, v) covers columns u*p..u*p+p-1, rows v*p..v*p+p-1 and has
  *               row-major id k = v*n_sub_x + u.  valid_idx lists the ids of the
@@ -52,10 +56,10 @@ typedef enum {
   SYNIM_E_NULL = -1,          /* a required pointer is NULL                      */
   SYNIM_E_SHAPE = -2,         /* inconsistent or unsupported sizes               */
   SYNIM_E_PARAM = -3,         /* invalid parameter value (e.g. magnification 0)  */
-  SYNIM_E_OOB = -4,           /* strict mode: samples fell outside the IF grid   */
+  SYNIM_E_OOB = -4,           /* strict check: samples fell outside the IF grid  */
   SYNIM_E_WORKSPACE = -5,     /* workspace missing or too small                  */
   SYNIM_E_HIP = -6,           /* a HIP runtime call failed                       */
-  SYNIM_E_NOT_CONVERGED = -7, /* Gauss-Newton hit its iteration limit            */
+  SYNIM_E_NOT_CONVERGED = -7, /* Gauss-Newton stopped without converging        */
   SYNIM_E_UNSUPPORTED = -8    /* no kernel variant for this geometry             */
 } synim_status;
 
@@ -191,9 +195,13 @@ int synim_im_vjp(const float* ifs, int n_act, int H_in, int W_in, const synim_af
  * with the same wfs, A and `planes` as the plan. */
 
 /* Fold the geometry into per-subaperture weight patches in `ws` (FP64 on the
- * device).  planes = 1 (IM) or 5 (IM + 4 Jacobian planes, dA required). */
+ * device).  planes = 1 (IM) or 5 (IM + 4 Jacobian planes, dA required).
+ * H_in, W_in: the IF grid the plan will stream, used only for the
+ * out-of-grid sample count (synim_plan_oob); both 0 leave it uncounted.
+ * Errors: SYNIM_E_NULL, SYNIM_E_SHAPE, SYNIM_E_PARAM, SYNIM_E_WORKSPACE,
+ *         SYNIM_E_UNSUPPORTED, SYNIM_E_HIP. */
 int synim_im_plan(const synim_wfs* wfs, const synim_affine* A, const synim_affine* dA, int planes,
-                  void* ws, size_t ws_bytes, void* stream);
+                  int H_in, int W_in, void* ws, size_t ws_bytes, void* stream);
 
 /* Stream n_act IFs through plane `plane` (0 = IM, 1..4 = d/dtheta_j) of a plan
  * built by synim_im_plan; out is device float32 [n_act][2N]. */
@@ -249,6 +257,18 @@ void synim_autotune_clear(void);
  * and synchronises `stream`. */
 int synim_plan_status(const void* ws, int* host_out, void* stream);
 
+/* Strict check of the out-of-grid reading (Sec. 2.1 leaves interpolation
+ * outside the IF grid open; the library zero-fills).  *host_count (host)
+ * receives the number of (valid subaperture, sample) pairs of the last plan
+ * built in `ws` (by synim_im_build, _jacobian, _vjp, _autotune, or
+ * synim_im_plan with a grid size) whose sample has a non-zero
+ * central-difference coefficient in that subaperture and a source point
+ * outside [0, W_in-1] x [0, H_in-1]; a sample two subapertures read counts
+ * twice.  Returns SYNIM_E_OOB when the count is non-zero (the plan and its
+ * IM are still complete, with those taps read as zero), SYNIM_OK otherwise.
+ * Synchronises `stream`.  Errors: SYNIM_E_NULL, SYNIM_E_HIP. */
+int synim_plan_oob(const void* ws, int64_t* host_count, void* stream);
+
 /* ------------------------------------------------------- multi-pair batch
  * Every (WFS, DM) pair of a multi-WFS system (e.g. 6 LGS WFS x 3 DMs) built in
  * one persistent launch - the multi-WFS batch of Sec. 4.2, where each DM's IF
@@ -288,7 +308,15 @@ int synim_batch_create(const synim_wfs* wfs, int n_wfs, const synim_dm* dms, int
                        const synim_pair* pairs, int n_pairs, void* ws, size_t ws_bytes,
                        void* stream, synim_batch** out);
 
-/* Upload new maps (host [n_pairs], pair order of creation) on `stream`. */
+/* Upload new maps (host [n_pairs], pair order of creation) on `stream`.
+ * Each map is checked on the host against the kernel configuration bound at
+ * creation: a map whose weight patches outgrow the bound kernel variant
+ * returns SYNIM_E_UNSUPPORTED (create a new batch); one whose tiles outgrow
+ * their staged-box bound re-binds the pair tables for the new maps (a
+ * captured graph is captured again on the next synim_batch_run_graph; the
+ * workspace must hold the new layout, else SYNIM_E_WORKSPACE).  Synchronises
+ * with the previous upload only.  Errors: SYNIM_E_NULL, SYNIM_E_PARAM
+ * (singular map), SYNIM_E_UNSUPPORTED, SYNIM_E_WORKSPACE, SYNIM_E_HIP. */
 int synim_batch_set_maps(synim_batch* b, const synim_affine* maps, void* stream);
 
 /* Enqueue the plans and the single stream launch of every pair. */
@@ -300,6 +328,11 @@ int synim_batch_run_graph(synim_batch* b, void* stream);
 
 /* OR of the pairs' plan status words (see synim_plan_status); synchronises. */
 int synim_batch_status(synim_batch* b, int* host_out, void* stream);
+
+/* Strict check of the last run (see synim_plan_oob): *host_count (host) =
+ * out-of-grid samples summed over the pairs; SYNIM_E_OOB when non-zero.
+ * Synchronises `stream`. */
+int synim_batch_oob(synim_batch* b, int64_t* host_count, void* stream);
 
 /* Time up to max_variants kernel variants on the batch (each pair with its
  * best tile shape for that variant) and keep the fastest; drops a captured
@@ -424,6 +457,13 @@ int synim_misreg_infer(synim_misreg_ctx* c, const float* slopes, int B, int mode
  * call (0 after an MLP-only or one-launch Gauss-Newton call, which build no
  * plans); synchronises. */
 int synim_misreg_status(synim_misreg_ctx* c, int* host_out, void* stream);
+/* Gauss-Newton convergence of the last synim_misreg_infer call: *host_n
+ * (host) = samples whose loop stopped without meeting tol (the iteration cap
+ * was reached, the normal matrix was singular, or the probe region left the
+ * context's bound; 0 after an MLP-only call).  Returns SYNIM_E_NOT_CONVERGED
+ * when *host_n > 0, SYNIM_OK otherwise; synchronises `stream`.
+ * Errors: SYNIM_E_NULL, SYNIM_E_HIP. */
+int synim_misreg_unconverged(synim_misreg_ctx* c, int32_t* host_n, void* stream);
 void synim_misreg_destroy(synim_misreg_ctx* c);
 
 #ifdef __cplusplus

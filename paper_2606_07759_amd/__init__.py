@@ -20,6 +20,9 @@ from . import _abi
 
 _LIB: Optional[C.CDLL] = None
 
+STATUS_OOB = -4              # SYNIM_E_OOB
+STATUS_NOT_CONVERGED = -7    # SYNIM_E_NOT_CONVERGED
+
 
 class SynimError(RuntimeError):
     def __init__(self, status: int, where: str):
@@ -242,15 +245,18 @@ def im_vjp(ifs, A, dA, wfs: Wfs, grad_im, ws=None):
     return out
 
 
-def im_plan(wfs: Wfs, A, dA=None, planes: int = 1, ws=None, device="cuda"):
-    """Build the folded-geometry plan in a (new or given) workspace tensor."""
+def im_plan(wfs: Wfs, A, dA=None, planes: int = 1, ws=None, device="cuda", grid=(0, 0)):
+    """Build the folded-geometry plan in a (new or given) workspace tensor.
+
+    ``grid`` = (H_in, W_in) of the IF stacks the plan will stream, for the
+    out-of-grid sample count of :func:`plan_oob`; (0, 0) leaves it uncounted."""
     lib = load()
     ws = _workspace(wfs, A, planes, ws, device)
     s = wfs.struct()
     a = _affine_struct(A)
     d = _dA_structs(dA) if dA is not None else None
-    _check(lib.synim_im_plan(C.byref(s), C.byref(a), d, planes, ws.data_ptr(), ws.numel(),
-                             _stream_handle(ws.device)), "im_plan")
+    _check(lib.synim_im_plan(C.byref(s), C.byref(a), d, planes, int(grid[0]), int(grid[1]),
+                             ws.data_ptr(), ws.numel(), _stream_handle(ws.device)), "im_plan")
     return ws
 
 
@@ -339,6 +345,19 @@ def plan_status(ws) -> int:
     return int(v.value)
 
 
+def plan_oob(ws) -> int:
+    """Out-of-grid samples of the last plan built in ``ws`` (synchronises).
+
+    The C call returns SYNIM_E_OOB when the count is non-zero (its strict
+    check); here the count itself is returned."""
+    lib = load()
+    v = C.c_int64(0)
+    rc = lib.synim_plan_oob(ws.data_ptr(), C.byref(v), _stream_handle(ws.device))
+    if rc != STATUS_OOB:
+        _check(rc, "plan_oob")
+    return int(v.value)
+
+
 # --------------------------------------------------------------- multi-pair
 class Batch:
     """Every (WFS, DM) pair of a multi-WFS system built in one persistent launch.
@@ -405,6 +424,14 @@ class Batch:
     def status(self) -> int:
         v = C.c_int(0)
         _check(load().synim_batch_status(self._h, C.byref(v), self._sh()), "batch_status")
+        return int(v.value)
+
+    def oob(self) -> int:
+        """Out-of-grid samples of the last run, summed over the pairs (synchronises)."""
+        v = C.c_int64(0)
+        rc = load().synim_batch_oob(self._h, C.byref(v), self._sh())
+        if rc != STATUS_OOB:
+            _check(rc, "batch_oob")
         return int(v.value)
 
     def autotune(self, max_variants: int = 6):
@@ -588,6 +615,15 @@ class Misreg:
         v = C.c_int(0)
         _check(load().synim_misreg_status(self._h, C.byref(v), _stream_handle(self.ws.device)),
                "misreg_status")
+        return int(v.value)
+
+    def unconverged(self) -> int:
+        """Samples of the last :meth:`infer` whose Gauss-Newton loop stopped without
+        converging (synchronises; the C call signals them with SYNIM_E_NOT_CONVERGED)."""
+        v = C.c_int32(0)
+        rc = load().synim_misreg_unconverged(self._h, C.byref(v), _stream_handle(self.ws.device))
+        if rc != STATUS_NOT_CONVERGED:
+            _check(rc, "misreg_unconverged")
         return int(v.value)
 
     def close(self):

@@ -72,10 +72,11 @@ SIGNATURES = {
     "synim_im_vjp": (I, [P, I, I, I, C.POINTER(SynimAffine), C.POINTER(SynimAffine),
                          C.POINTER(SynimWfs), P, P, P, SZ, P]),
     "synim_im_plan": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(SynimAffine),
-                          I, P, SZ, P]),
+                          I, I, I, P, SZ, P]),
     "synim_im_apply": (I, [P, I, I, I, C.POINTER(SynimAffine), C.POINTER(SynimWfs), I, I, P, P,
                            SZ, P]),
     "synim_plan_status": (I, [P, C.POINTER(I), P]),
+    "synim_plan_oob": (I, [P, C.POINTER(C.c_int64), P]),
     "synim_im_autotune": (I, [P, I, I, I, C.POINTER(SynimAffine), C.POINTER(SynimWfs), P, P, SZ,
                               I, C.POINTER(C.c_float), C.POINTER(I), P]),
     "synim_im_config": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(I)]),
@@ -88,6 +89,7 @@ SIGNATURES = {
     "synim_batch_run": (I, [P, P]),
     "synim_batch_run_graph": (I, [P, P]),
     "synim_batch_status": (I, [P, C.POINTER(I), P]),
+    "synim_batch_oob": (I, [P, C.POINTER(C.c_int64), P]),
     "synim_batch_autotune": (I, [P, I, C.POINTER(C.c_float), C.POINTER(I), P]),
     "synim_batch_config": (I, [P, C.POINTER(I)]),
     "synim_batch_destroy": (None, [P]),
@@ -103,6 +105,7 @@ SIGNATURES = {
     "synim_misreg_features": (I, [P, P, I, P, P, P, P]),
     "synim_misreg_infer": (I, [P, P, I, I, P, P, I, I, P]),
     "synim_misreg_status": (I, [P, C.POINTER(I), P]),
+    "synim_misreg_unconverged": (I, [P, C.POINTER(C.c_int32), P]),
     "synim_misreg_destroy": (None, [P]),
     "synim_im_candidates": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(I), I,
                                 C.POINTER(I)]),

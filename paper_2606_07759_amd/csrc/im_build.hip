@@ -63,7 +63,8 @@ struct PlanJob {
   int n_sub_x, n_sub_y, p, nv;
   int PH, PW, n_planes, cap_floats;
   int TX, TY, NSLOT, n_tiles_x;
-  int n_tiles, BHmax, pad0, pad1;
+  int n_tiles, BHmax;
+  int H_in, W_in;             // IF grid, for the out-of-grid count (0: not counted)
   int2* origin;
   int2* hrows;                // [nv] patch rows [x, y) holding a non-zero weight
   double* inv2nk;
@@ -81,6 +82,12 @@ template <bool TABLE>
 __device__ __forceinline__ const PlanJob& job_of(const PlanJob& one, const PlanJob* jobs) {
   if constexpr (TABLE) return jobs[blockIdx.y];
   else return one;
+}
+
+// Whether pixel (x, y) is a pupil pixel of the subaperture with corner (x0, y0).
+__device__ __forceinline__ int in_sub(const uint8_t* __restrict__ pupil, int W, int x0, int y0,
+                                      int p, int x, int y) {
+  return (x >= x0 && x < x0 + p && y >= y0 && y < y0 + p && pupil[(size_t)y * W + x]) ? 1 : 0;
 }
 
 // Origin (patch corner) and 1/(2 n_k) of each valid subaperture: one wave
@@ -128,7 +135,25 @@ __global__ __launch_bounds__(PLAN_SUBAPS_BLOCK) void plan_subaps_kernel(
     nk += J.pupil[(size_t)y * W + x] ? 1 : 0;
   }
   for (int o = 32; o >= 1; o >>= 1) nk += __shfl_xor(nk, o, 64);
+  // samples this subaperture's central differences read (a non-zero c_x or
+  // c_y) whose source point lies outside the IF grid: their bilinear taps
+  // are zero-filled
+  int oob = 0;
+  if (J.W_in > 0) {
+    const int x0 = u * p, y0 = v * p;
+    for (int i = lane; i < hw * hw; i += 64) {
+      const int y = y0 - 1 + i / hw, x = x0 - 1 + i % hw;
+      const int cx = in_sub(J.pupil, W, x0, y0, p, x - 1, y) - in_sub(J.pupil, W, x0, y0, p, x + 1, y);
+      const int cy = in_sub(J.pupil, W, x0, y0, p, x, y - 1) - in_sub(J.pupil, W, x0, y0, p, x, y + 1);
+      if (cx == 0 && cy == 0) continue;
+      double xs, ys;
+      src_xy(m, x, y, xs, ys);
+      if (!(xs >= 0.0 && xs <= J.W_in - 1.0 && ys >= 0.0 && ys <= J.H_in - 1.0)) ++oob;
+    }
+    for (int o = 32; o >= 1; o >>= 1) oob += __shfl_xor(oob, o, 64);
+  }
   if (lane != 0) return;
+  if (oob > 0) atomicAdd(J.status + 2, oob);
   int ox = 0, oy = 0;
   if (fabs(xmin) < 1e9 && fabs(xmax) < 1e9 && fabs(ymin) < 1e9 && fabs(ymax) < 1e9) {
     ox = (int)floor(xmin);
@@ -145,10 +170,6 @@ __global__ __launch_bounds__(PLAN_SUBAPS_BLOCK) void plan_subaps_kernel(
   J.inv2nk[kk] = nk > 0 ? 1.0 / (2.0 * nk) : 0.0;
 }
 
-__device__ __forceinline__ int in_sub(const uint8_t* __restrict__ pupil, int W, int x0, int y0,
-                                      int p, int x, int y) {
-  return (x >= x0 && x < x0 + p && y >= y0 && y < y0 + p && pupil[(size_t)y * W + x]) ? 1 : 0;
-}
 
 // Weight patch entry gid = (valid subaperture, patch entry): gathers, in a
 // fixed order, every haloed-window sample q whose bilinear cell has this entry
@@ -537,6 +558,19 @@ void patch_need(const synim_affine& A, int p, int* pw, int* ph) {
   *ph = (int)std::floor(ay * (p + 1) + 1e-7) + 3;
 }
 
+// Staged-box bound (floats per row BW, rows BH) of a tx x ty tile of variant
+// v under map A: a subaperture's patch origin is the floor of an affine
+// function of (u*p, v*p), so over a tile the origins spread by at most the
+// map's stretch of the tile + 1; only the patch rows holding a weight are
+// staged (at most ph_need of the PH), columns over the full patch width.
+void tile_bound(const synim_affine& A, int p, const Variant& v, int tx, int ty, int ph_need,
+                int* bw, int* bh) {
+  const double sx = std::fabs(A.A[0][0]) * p * (tx - 1) + std::fabs(A.A[0][1]) * p * (ty - 1);
+  const double sy = std::fabs(A.A[1][0]) * p * (tx - 1) + std::fabs(A.A[1][1]) * p * (ty - 1);
+  *bw = ((int)std::floor(sx + 1e-6) + 1 + v.PW + 3 + 3) / 4 * 4;
+  *bh = (int)std::floor(sy + 1e-6) + 1 + ph_need;
+}
+
 // Tile shapes of one variant for this geometry, cheapest first by the cost
 // model: staged IF floats per subaperture (a partial 128-byte line counted at
 // each row end), for tiles whose packed rows provably fit the stage buffers.
@@ -552,14 +586,8 @@ int tiles_for_variant(const synim_wfs& w, const synim_affine& A, const Variant& 
   for (int ns = nslot_max; ns >= nslot_max / 4; ns /= 2)
     for (int tx = 1; tx <= ns; tx *= 2) {
       const int ty = ns / tx;
-      // a subaperture's patch origin is the floor of an affine function of
-      // (u*p, v*p), so over a tile the origins spread by at most these + 1
-      const double sx = std::fabs(A.A[0][0]) * p * (tx - 1) + std::fabs(A.A[0][1]) * p * (ty - 1);
-      const double sy = std::fabs(A.A[1][0]) * p * (tx - 1) + std::fabs(A.A[1][1]) * p * (ty - 1);
-      // only the patch rows holding a weight are staged: at most ph_need of
-      // the PH (columns are staged over the full patch width)
-      const int BW = ((int)std::floor(sx + 1e-6) + 1 + v.PW + 3 + 3) / 4 * 4;
-      const int BH = (int)std::floor(sy + 1e-6) + 1 + ph_need;
+      int BW, BH;
+      tile_bound(A, p, v, tx, ty, ph_need, &BW, &BH);
       if ((long)BH * BW > v.cap_floats() || BH > MAX_TILE_ROWS) continue;
       const int ux = std::min(tx, w.n_sub_x), uy = std::min(ty, w.n_sub_y);
       const double fill = (double)(ux * uy) / ns;   // lanes with a subaperture
@@ -765,19 +793,21 @@ size_t max_layout(const synim_wfs& w, const synim_affine& A, int planes) {
 }
 
 int build_plan_with(const synim_wfs& w, const synim_affine& A, const synim_affine* dA, int planes,
-                    void* ws, size_t ws_bytes, hipStream_t st, Plan* P);
+                    int H_in, int W_in, void* ws, size_t ws_bytes, hipStream_t st, Plan* P);
 int enqueue_plan(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map4& dm, int planes,
-                 const Plan& P, hipStream_t st);
+                 int H_in, int W_in, const Plan& P, hipStream_t st);
 
+// H_in, W_in: the IF grid the plan will stream, for the out-of-grid sample
+// count (status word 2); 0 leaves it uncounted.
 int build_plan(const synim_wfs& w, const synim_affine& A, const synim_affine* dA, int planes,
-               void* ws, size_t ws_bytes, hipStream_t st, Plan* P) {
+               int H_in, int W_in, void* ws, size_t ws_bytes, hipStream_t st, Plan* P) {
   int rc = choose_dims(w, A, &P->d);
   if (rc != SYNIM_OK) return rc;
-  return build_plan_with(w, A, dA, planes, ws, ws_bytes, st, P);
+  return build_plan_with(w, A, dA, planes, H_in, W_in, ws, ws_bytes, st, P);
 }
 
 int build_plan_with(const synim_wfs& w, const synim_affine& A, const synim_affine* dA, int planes,
-                    void* ws, size_t ws_bytes, hipStream_t st, Plan* P) {
+                    int H_in, int W_in, void* ws, size_t ws_bytes, hipStream_t st, Plan* P) {
   P->L = layout(w, P->d, planes);
   if (!ws) return SYNIM_E_WORKSPACE;
   if (ws_bytes < P->L.total) return SYNIM_E_WORKSPACE;
@@ -788,12 +818,12 @@ int build_plan_with(const synim_wfs& w, const synim_affine& A, const synim_affin
   Map4 dm{};
   if (planes > 1)
     for (int j = 0; j < 4; ++j) dm.m[j] = to_map(dA[j]);
-  return enqueue_plan(w, m, nullptr, dm, planes, *P, st);
+  return enqueue_plan(w, m, nullptr, dm, planes, H_in, W_in, *P, st);
 }
 
 // The plan job of one pair: its WFS, plan regions and kernel dimensions.
 PlanJob make_job(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map4& dm,
-                 const Map4* dm_dev, int planes, const Plan& P) {
+                 const Map4* dm_dev, int planes, const Plan& P, int H_in, int W_in) {
   const Dims& d = P.d;
   PlanJob J{};
   J.m = m;
@@ -816,6 +846,8 @@ PlanJob make_job(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map
   J.n_tiles_x = d.n_tiles_x;
   J.n_tiles = d.n_tiles;
   J.BHmax = d.BHmax;
+  J.H_in = H_in;
+  J.W_in = W_in;
   J.origin = P.origin();
   J.hrows = P.hrows();
   J.inv2nk = P.inv2nk();
@@ -876,8 +908,8 @@ int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv
 }
 
 int enqueue_plan(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map4& dm, int planes,
-                 const Plan& P, hipStream_t st) {
-  const PlanJob J = make_job(w, m, m_dev, dm, nullptr, planes, P);
+                 int H_in, int W_in, const Plan& P, hipStream_t st) {
+  const PlanJob J = make_job(w, m, m_dev, dm, nullptr, planes, P, H_in, W_in);
   return enqueue_plans(J, nullptr, 1, J.nv, J.PH * J.PW, J.n_tiles, J.n_planes, st);
 }
 
@@ -1045,7 +1077,7 @@ extern "C" int synim_im_autotune(const float* ifs, int n_act, int H_in, int W_in
   for (int c = 0; c < n && rc == SYNIM_OK; ++c) {
     Plan P{};
     P.d = cand[c];
-    rc = build_plan_with(*wfs, *A, nullptr, 1, ws, ws_bytes, st, &P);
+    rc = build_plan_with(*wfs, *A, nullptr, 1, H_in, W_in, ws, ws_bytes, st, &P);
     if (rc != SYNIM_OK) break;
     rc = launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);   // warm
     if (rc != SYNIM_OK) break;
@@ -1148,7 +1180,7 @@ extern "C" int synim_im_build(const float* ifs, int n_act, int H_in, int W_in,
   if (!im) return SYNIM_E_NULL;
   hipStream_t st = (hipStream_t)stream;
   Plan P{};
-  rc = build_plan(*wfs, *A, nullptr, 1, ws, ws_bytes, st, &P);
+  rc = build_plan(*wfs, *A, nullptr, 1, H_in, W_in, ws, ws_bytes, st, &P);
   if (rc != SYNIM_OK) return rc;
   return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);
 }
@@ -1162,7 +1194,7 @@ extern "C" int synim_im_jacobian(const float* ifs, int n_act, int H_in, int W_in
   if (!dA || !dim) return SYNIM_E_NULL;
   hipStream_t st = (hipStream_t)stream;
   Plan P{};
-  rc = build_plan(*wfs, *A, dA, 5, ws, ws_bytes, st, &P);
+  rc = build_plan(*wfs, *A, dA, 5, H_in, W_in, ws, ws_bytes, st, &P);
   if (rc != SYNIM_OK) return rc;
   if (im) {
     rc = launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);
@@ -1180,7 +1212,7 @@ extern "C" int synim_im_vjp(const float* ifs, int n_act, int H_in, int W_in,
   if (!dA || !grad_im || !grad_theta) return SYNIM_E_NULL;
   hipStream_t st = (hipStream_t)stream;
   Plan P{};
-  rc = build_plan(*wfs, *A, dA, 5, ws, ws_bytes, st, &P);
+  rc = build_plan(*wfs, *A, dA, 5, H_in, W_in, ws, ws_bytes, st, &P);
   if (rc != SYNIM_OK) return rc;
   int G = 0;
   rc = launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 1, 4, nullptr, grad_im, st, &G);
@@ -1192,15 +1224,16 @@ extern "C" int synim_im_vjp(const float* ifs, int n_act, int H_in, int W_in,
 }
 
 extern "C" int synim_im_plan(const synim_wfs* wfs, const synim_affine* A,
-                             const synim_affine* dA, int planes, void* ws, size_t ws_bytes,
-                             void* stream) {
+                             const synim_affine* dA, int planes, int H_in, int W_in, void* ws,
+                             size_t ws_bytes, void* stream) {
   if (!A) return SYNIM_E_NULL;
   int rc = validate_wfs(wfs);
   if (rc != SYNIM_OK) return rc;
   if (planes != 1 && planes != 5) return SYNIM_E_PARAM;
   if (planes == 5 && !dA) return SYNIM_E_NULL;
+  if (H_in < 0 || W_in < 0 || (H_in == 0) != (W_in == 0)) return SYNIM_E_SHAPE;
   Plan P{};
-  return build_plan(*wfs, *A, dA, planes, ws, ws_bytes, (hipStream_t)stream, &P);
+  return build_plan(*wfs, *A, dA, planes, H_in, W_in, ws, ws_bytes, (hipStream_t)stream, &P);
 }
 
 extern "C" int synim_im_apply(const float* ifs, int n_act, int H_in, int W_in,
@@ -1226,6 +1259,16 @@ extern "C" int synim_plan_status(const void* ws, int* host_out, void* stream) {
                                (hipStream_t)stream));
   SYNIM_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
   return SYNIM_OK;
+}
+
+extern "C" int synim_plan_oob(const void* ws, int64_t* host_count, void* stream) {
+  if (!ws || !host_count) return SYNIM_E_NULL;
+  int n = 0;
+  SYNIM_HIP_TRY(hipMemcpyAsync(&n, static_cast<const int*>(ws) + 2, sizeof(int),
+                               hipMemcpyDeviceToHost, (hipStream_t)stream));
+  SYNIM_HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  *host_count = n;
+  return n > 0 ? SYNIM_E_OOB : SYNIM_OK;
 }
 
 // ------------------------------------------------------------------- batches
@@ -1586,7 +1629,7 @@ int batch_bind(synim_batch* b, const Variant& v, hipStream_t st) {
     const Map4* dmaps_dev =
         b->planes > 1 ? reinterpret_cast<const Map4*>(b->ws + b->off_dmaps) + i : nullptr;
     jobs[pos] = make_job(b->wfs[pr.wfs], to_map(pr.A), maps_dev + i, Map4{}, dmaps_dev,
-                         b->planes, b->plans[i]);
+                         b->planes, b->plans[i], b->dms[pr.dm].H_in, b->dms[pr.dm].W_in);
     b->max_nv = std::max(b->max_nv, jobs[pos].nv);
     b->max_e = std::max(b->max_e, jobs[pos].PH * jobs[pos].PW);
     b->max_tiles = std::max(b->max_tiles, jobs[pos].n_tiles);
@@ -1813,7 +1856,31 @@ extern "C" int synim_batch_set_maps(synim_batch* b, const synim_affine* maps, vo
     const double det = maps[i].A[0][0] * maps[i].A[1][1] - maps[i].A[0][1] * maps[i].A[1][0];
     if (!(std::fabs(det) > 1e-12)) return SYNIM_E_PARAM;
   }
-  if (b->shared && !shared_maps_fit(b, maps)) {
+  // The kernel variant (patch size) and each pair's tile shape were chosen for
+  // the maps at creation.  A map whose patches no longer fit the variant needs
+  // a new batch; one whose tiles outgrow their staged-box bound re-binds the
+  // pair tables for the new maps (and drops a captured graph).
+  bool rebind = false;
+  if (b->var) {
+    const Variant& v = *b->var;
+    for (int i = 0; i < np; ++i) {
+      const int p = b->wfs[b->pairs[i].wfs].p;
+      int pw, ph;
+      patch_need(maps[i], p, &pw, &ph);
+      if (pw > v.PW || ph > v.PH()) return SYNIM_E_UNSUPPORTED;
+      if (b->shared || (int)b->plans.size() != np) continue;
+      const Dims& d = b->plans[i].d;
+      int bw, bh;
+      tile_bound(maps[i], p, v, d.TX, d.TY, ph, &bw, &bh);
+      if (bh > d.BHmax || (long)bw * bh > v.cap_floats() || bh > MAX_TILE_ROWS) rebind = true;
+    }
+  }
+  if (rebind) {
+    for (int i = 0; i < np; ++i) b->pairs[i].A = maps[i];
+    const int rc = batch_bind(b, *b->var, st);
+    if (rc != SYNIM_OK) return rc;
+    batch_drop_graph(b);
+  } else if (b->shared && !shared_maps_fit(b, maps)) {
     // a subaperture moved past the margin of its shared tile: re-bin for the
     // new maps (a captured graph is captured again on the next run)
     for (int i = 0; i < np; ++i) b->pairs[i].A = maps[i];
@@ -1871,6 +1938,20 @@ extern "C" int synim_batch_status(synim_batch* b, int* host_out, void* stream) {
   for (int x : s) v |= x;
   *host_out = v;
   return SYNIM_OK;
+}
+
+extern "C" int synim_batch_oob(synim_batch* b, int64_t* host_count, void* stream) {
+  if (!b || !host_count) return SYNIM_E_NULL;
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<int> n(b->plans.size(), 0);
+  for (size_t i = 0; i < b->plans.size(); ++i)
+    SYNIM_HIP_TRY(hipMemcpyAsync(&n[i], b->plans[i].status() + 2, sizeof(int),
+                                 hipMemcpyDeviceToHost, st));
+  SYNIM_HIP_TRY(hipStreamSynchronize(st));
+  int64_t t = 0;
+  for (int x : n) t += x;
+  *host_count = t;
+  return t > 0 ? SYNIM_E_OOB : SYNIM_OK;
 }
 
 extern "C" int synim_batch_autotune(synim_batch* b, int max_variants, float* times_ms,

@@ -230,6 +230,7 @@ def evaluate(system: ProbeSystem, trained: Trained, seeds, batch: int = 1000,
     est = estimator(system, trained, max_batch=batch, max_iter=max_iter)
     res = {MISREG_GN: [], MISREG_MLP: [], MISREG_MLP_GN: []}
     its = {MISREG_GN: [], MISREG_MLP_GN: []}
+    unconv = {MISREG_GN: 0, MISREG_MLP_GN: 0}
     for a in range(0, n, batch):
         b = min(n, a + batch)
         s = slopes[a:b].contiguous()
@@ -238,6 +239,7 @@ def evaluate(system: ProbeSystem, trained: Trained, seeds, batch: int = 1000,
             res[mode].append(th.cpu().numpy())
             if mode in its:
                 its[mode].append(it.cpu().numpy())
+                unconv[mode] += est.unconverged()
     for k in res:
         res[k] = np.concatenate(res[k])
     for k in its:
@@ -262,7 +264,9 @@ def evaluate(system: ProbeSystem, trained: Trained, seeds, batch: int = 1000,
         "gn_iters_max": int(its[MISREG_GN].max()),
         "mlp_gn_iters_mean": float(its[MISREG_MLP_GN].mean()),
         "mlp_gn_iters_max": int(its[MISREG_MLP_GN].max()),
-        "gn_unconverged": int(np.sum(its[MISREG_GN] >= max_iter)),
+        "gn_unconverged": int(unconv[MISREG_GN]),
+        "mlp_gn_unconverged": int(unconv[MISREG_MLP_GN]),
+        "gn_capped_seeds": [int(v) for v in seeds[its[MISREG_GN] >= max_iter]],
     }
     timing = {}
     for bsz in (1, min(batch, n)):

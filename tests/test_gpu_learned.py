@@ -92,6 +92,50 @@ def test_mlp_forward_backward_parity(gpu_lib, B):
     assert np.all(W1[:, mask] == 0)
 
 
+@pytest.mark.parametrize("B", [1, 256])
+def test_mlp_parity_estimator_shape(gpu_lib, B):
+    """The estimator's own network, 2 x 4000 -> 512 -> 256 -> 4, fed the compact
+    inputs of the learned-fit workload (20 probes x 52 subapertures per channel,
+    2080 non-zero inputs of 8000), He-initialised as in training: forward and
+    MSE backward against the FP64 oracle net on the zero-padded 8000 inputs."""
+    import torch
+    from paper_2606_07759_amd import learned
+    S = gpu_lib
+    say(f"[case] mlp estimator shape B={B}")
+    nN = 20 * 52
+    net = S.Mlp(8000, 512, 256, 4, ((0, nN), (4000, nN)))
+    packed = learned.he_init(net, 12)
+    rng = np.random.default_rng(200 + B)
+    # non-zero biases, so their gradients and the ReLU masks are exercised
+    for (lo, hi), is_bias in zip(net.layout(), (False, True) * 3):
+        if is_bias:
+            packed[lo:hi] = (0.05 * rng.standard_normal(hi - lo)).astype(np.float32)
+    xc = rng.standard_normal((B, 2 * nN)).astype(np.float32)
+    t = rng.uniform(-1, 1, (B, 4)).astype(np.float32)
+    dev = torch.device("cuda:0")
+    params = torch.from_numpy(packed).to(dev)
+    scratch = net.scratch(B, device=dev)
+    y = net.forward(params, torch.from_numpy(xc).to(dev), scratch)
+    grads = torch.empty_like(params)
+    net.backward(params, torch.from_numpy(xc).to(dev), scratch, y, torch.from_numpy(t).to(dev),
+                 grads)
+    torch.cuda.synchronize()
+    lay = net.layout()
+    shapes = [(512, 8000), (512,), (256, 512), (256,), (4, 256), (4,)]
+    P = [packed[lo:hi].astype(np.float64).reshape(sh) for (lo, hi), sh in zip(lay, shapes)]
+    oparams = [(P[0], P[1]), (P[2], P[3]), (P[4], P[5])]
+    x = np.zeros((B, 8000))
+    x[:, :nN] = xc[:, :nN]
+    x[:, 4000:4000 + nN] = xc[:, nN:]
+    yref, acts = omlp.forward(x, oparams)
+    assert rel_err(y.cpu().numpy(), yref) <= 1e-4
+    gref = omlp.backward(acts, oparams, t.astype(np.float64))
+    g = grads.cpu().numpy()
+    for (lo, hi), ref in zip(lay, [a for pair in gref for a in pair]):
+        got = g[lo:hi].reshape(ref.shape)
+        assert rel_err(got, ref) <= 1e-4, (lo, hi, rel_err(got, ref))
+
+
 def test_adam_step_parity(gpu_lib):
     import torch
     S = gpu_lib

@@ -15,6 +15,8 @@ import sys
 import numpy as np
 import pytest
 
+import oracle_pool
+
 pytestmark = pytest.mark.gpu
 
 
@@ -42,8 +44,10 @@ def test_learned_estimator_gain(gpu_lib):
     # prior: theta0 against labels drawn uniformly -> RMS of U(-1, 1) = 0.577 subaperture
     assert max(rep["rms_mlp_vs_truth"][:2]) < 0.25
     assert max(rep["rms_mlp_gn_vs_gn"]) < 1e-3
-    # a few samples end their 20 iterations hopping between bilinear cells at
-    # the minimum (the model's gradient is piecewise constant there)
-    assert rep["gn_unconverged"] <= 4
+    # samples that end their 20 iterations at the cap (hopping between bilinear
+    # cells at the minimum: the model's gradient is piecewise constant there)
+    # fail in the FP64 oracle's Gauss-Newton too
+    for s in rep["gn_capped_seeds"]:
+        assert not oracle_pool.oracle_gn_sample(s)[2], s
     assert rep["mlp_gn_iters_mean"] < rep["gn_iters_mean"]
     torch.cuda.synchronize()
