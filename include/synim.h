@@ -168,6 +168,26 @@ int synim_im_workspace(const synim_wfs* wfs, const synim_affine* A, int planes, 
 int synim_im_build(const float* ifs, int n_act, int H_in, int W_in, const synim_affine* A,
                    const synim_wfs* wfs, float* im, void* ws, size_t ws_bytes, void* stream);
 
+/* Largest plan synim_im_build_noalloc holds: 16 MiB (the 80x80-subaperture
+ * ELT build under a +-1 deg map needs 5.1 MB). */
+#define SYNIM_NOALLOC_WS_BYTES (16u << 20)
+
+/* synim_im_build for callers that cannot allocate device memory or pass a
+ * workspace (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  Same arguments, result and kernels as
+ * synim_im_build, without ws / ws_bytes: the plan lives in one fixed device
+ * array of SYNIM_NOALLOC_WS_BYTES per GPU, held from the library's first use
+ * on that GPU until the process ends.  Allocates nothing (no hipMalloc, no
+ * allocating library call).  Every call on one GPU shares that array and
+ * overwrites it: calls that overlap on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller; the array's contents
+ * after a call are the last call's plan (status words at its start, see
+ * synim_plan_status, not reachable through this entry point).
+ * Errors: as synim_im_build; SYNIM_E_WORKSPACE when the geometry's plan
+ * exceeds SYNIM_NOALLOC_WS_BYTES. */
+int synim_im_build_noalloc(const float* ifs, int n_act, int H_in, int W_in, const synim_affine* A,
+                           const synim_wfs* wfs, float* im, void* stream);
+
 /* IM and its Jacobian with respect to theta_j (j = 0..3) for the derivative
  * maps dA (from synim_affine_from_misreg):
  *   d phi / d theta_j = grad bilinear(F, p_s) . (dA[j].A p_o + dA[j].b)

@@ -1185,6 +1185,54 @@ extern "C" int synim_im_build(const float* ifs, int n_act, int H_in, int W_in,
   return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);
 }
 
+// ------------------------------------------------- build without allocation
+// A fixed device array holds the plan of synim_im_build_noalloc, so that call
+// needs no workspace and allocates nothing.  In host code `scratch` names a
+// host-side stand-in, not device memory: its device address is looked up once
+// per device with hipGetSymbolAddress and only that address is passed on.
+namespace {
+constexpr size_t kNoallocBytes = (size_t)SYNIM_NOALLOC_WS_BYTES;
+static __device__ __align__(256) unsigned char scratch[kNoallocBytes];
+constexpr int kNoallocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoallocDevices] = {};
+
+// Device address of this device's `scratch` (looked up on the first call).
+int noalloc_scratch(void** out) {
+  int dev = 0;
+  SYNIM_HIP_TRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoallocDevices) return SYNIM_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    SYNIM_HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return SYNIM_E_HIP;
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return SYNIM_OK;
+}
+}  // namespace
+
+extern "C" int synim_im_build_noalloc(const float* ifs, int n_act, int H_in, int W_in,
+                                      const synim_affine* A, const synim_wfs* wfs, float* im,
+                                      void* stream) {
+  int rc = check_common(ifs, n_act, H_in, W_in, A, wfs);
+  if (rc != SYNIM_OK) return rc;
+  if (!im) return SYNIM_E_NULL;
+  Plan P{};
+  rc = choose_dims(*wfs, *A, &P.d);
+  if (rc != SYNIM_OK) return rc;
+  if (layout(*wfs, P.d, 1).total > kNoallocBytes) return SYNIM_E_WORKSPACE;
+  void* ws = nullptr;
+  rc = noalloc_scratch(&ws);
+  if (rc != SYNIM_OK) return rc;
+  hipStream_t st = (hipStream_t)stream;
+  rc = build_plan_with(*wfs, *A, nullptr, 1, H_in, W_in, ws, kNoallocBytes, st, &P);
+  if (rc != SYNIM_OK) return rc;
+  return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);
+}
+
 extern "C" int synim_im_jacobian(const float* ifs, int n_act, int H_in, int W_in,
                                  const synim_affine* A, const synim_affine* dA,
                                  const synim_wfs* wfs, float* im, float* dim, void* ws,
