@@ -29,7 +29,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "IM columns/s & % HBM roofline; misreg-fit ms, learned vs Gauss-Newton"
 PEAK_HBM_GBS = 8000.0
-STREAM_SRC = os.path.join(ROOT, "paper_2606_07759_amd", "csrc", "im_build.hip")
+STREAM_SRC = os.path.join(ROOT, "paper_2606_07759_amd", "csrc", "stream.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "im_stream_elt_traffic.json")
 
 

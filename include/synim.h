@@ -292,8 +292,11 @@ int synim_plan_oob(const void* ws, int64_t* host_count, void* stream);
 /* ------------------------------------------------------- multi-pair batch
  * Every (WFS, DM) pair of a multi-WFS system (e.g. 6 LGS WFS x 3 DMs) built in
  * one persistent launch - the multi-WFS batch of Sec. 4.2, where each DM's IF
- * stack is fetched once for all the WFS that see it: pairs sharing a DM read
- * each chunk of its stack side by side.  Pairs may have their own map (cone
+ * stack is fetched once for all the WFS that see it: for IM batches
+ * (planes = 1) the subapertures of every WFS of a DM are binned by the cell
+ * of the IF grid their weight patches start in, and one staging of a cell's
+ * IF rows serves all of them (the tiles' staged boxes overlap by the patch
+ * halo, so HBM reads a DM's stack about twice rather than once per WFS).  Pairs may have their own map (cone
  * effect, off-axis footprint), WFS (uneven valid-subaperture counts) and DM
  * (uneven actuator counts).  The maps live in device memory, so a graph
  * captured by synim_batch_run_graph replays after synim_batch_set_maps

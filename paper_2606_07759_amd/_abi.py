@@ -4,7 +4,9 @@ from __future__ import annotations
 import ctypes as C
 import os
 
-LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsynim.so")
+# the in-tree build; SYNIM_LIB names another build of the same sources
+LIB_PATH = os.environ.get(
+    "SYNIM_LIB", os.path.join(os.path.dirname(os.path.abspath(__file__)), "libsynim.so"))
 
 
 class SynimAffine(C.Structure):
@@ -119,6 +121,11 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise RuntimeError(
             f"HIP library not found at {path}; build it with `python -m paper_2606_07759_amd.build`")
+    # torch first: its HIP runtime is then the one libsynim.so binds to (same
+    # soname).  Loaded the other way round, the process would hold two HIP
+    # runtimes, and torch's streams and allocations would be foreign to the
+    # library's (its host copies of torch device memory fail).
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

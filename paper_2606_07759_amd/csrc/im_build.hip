@@ -1812,12 +1812,13 @@ void batch_fill(synim_batch* b, const synim_wfs* wfs, int n_wfs, const synim_dm*
 }
 
 // Shared tiles when some DM group holds several single-plane pairs; the
-// WFS valid lists come to the host for the binning.  Off: its one GPU run gave
-// wrong values and a memory fault.  That run's DMA instructions read their
-// buffer resource one wait state after the v_readfirstlane that wrote it (5
-// are needed), so a DMA could stream from a stale address; the DMA padding in
-// the stream kernel removes that hazard.
-constexpr bool kSharedTiles = false;
+// WFS valid lists come to the host for the binning.  (An earlier build of this
+// path gave wrong values and a memory fault: its DMA instructions read their
+// buffer resource one wait state after the v_readfirstlane that wrote it, where
+// 5 are needed, so a DMA could stream from a stale or half-updated address.
+// The DMA padding in the stream kernel removes that hazard, and a CPU test
+// checks the wait states of every LDS DMA in the built assembly.)
+constexpr bool kSharedTiles = true;
 int batch_pick_shared(synim_batch* b) {
   b->shared = false;
   if (!kSharedTiles || b->planes != 1) return SYNIM_OK;
