@@ -168,6 +168,32 @@ int synim_im_workspace(const synim_wfs* wfs, const synim_affine* A, int planes, 
 int synim_im_build(const float* ifs, int n_act, int H_in, int W_in, const synim_affine* A,
                    const synim_wfs* wfs, float* im, void* ws, size_t ws_bytes, void* stream);
 
+/* Interaction matrix of a pre-masked IF stack with edge repair (Sec. 2.3).
+ * The IFs were multiplied by a DM-side mask M on the IF grid, so the single
+ * bilinear interpolation softens the mask edge and the warped phase collapses
+ * towards zero there.  For every haloed WFS sample q (x in [-1, W], y in
+ * [-1, H]) the warped mask m(q) = bilinear(M, A q + b) gives:
+ *   1. the strict core S = {m >= threshold} (the paper uses 0.999999), whose
+ *      phase is kept; every other sample is cleared;
+ *   2. the edge ring E = dilate(S) \ S, dilation by the 4-neighbour cross;
+ *   3. for e in E and each direction d in {+x, -x, +y, -y} with P1 = e + d in
+ *      S: the estimate 2 phi(P1) - phi(P2) if P2 = e + 2d is in S too, else
+ *      phi(P1); phi(e) = the mean of the estimates of the valid directions.
+ * Samples outside the haloed window count as outside S.  The slopes of the
+ * repaired phase then follow as in synim_im_build.  The repair is linear in
+ * the phase for a fixed mask, so it is folded into the plan's FP64 weights
+ * and the IF stack is still streamed once.
+ *   dm_mask   device uint8 [H_in][W_in], 0/1 (M)
+ *   threshold in (0, 1]
+ *   ws        device workspace of at least synim_im_repaired_workspace bytes
+ * Errors: SYNIM_E_NULL, SYNIM_E_SHAPE, SYNIM_E_PARAM (threshold),
+ *         SYNIM_E_WORKSPACE, SYNIM_E_UNSUPPORTED, SYNIM_E_HIP. */
+int synim_im_repaired_workspace(const synim_wfs* wfs, const synim_affine* A, size_t* bytes);
+int synim_im_build_repaired(const float* ifs, int n_act, int H_in, int W_in,
+                            const uint8_t* dm_mask, double threshold, const synim_affine* A,
+                            const synim_wfs* wfs, float* im, void* ws, size_t ws_bytes,
+                            void* stream);
+
 /* Largest plan synim_im_build_noalloc holds: 16 MiB (the 80x80-subaperture
  * ELT build under a +-1 deg map needs 5.1 MB). */
 #define SYNIM_NOALLOC_WS_BYTES (16u << 20)

@@ -202,6 +202,31 @@ def im_build(ifs, A, wfs: Wfs, out=None, ws=None):
     return out
 
 
+def im_build_repaired(ifs, dm_mask, A, wfs: Wfs, threshold: float = 0.999999, out=None, ws=None):
+    """IM of a pre-masked IF stack with the edge repair of Sec. 2.3 (see
+    ``synim_im_build_repaired``); ``dm_mask`` is the DM-side 0/1 mask [H_in][W_in]."""
+    torch = _torch()
+    lib = load()
+    _dev_f32(ifs, "ifs")
+    n, H_in, W_in = ifs.shape
+    if tuple(dm_mask.shape) != (H_in, W_in) or dm_mask.dtype != torch.uint8 or not dm_mask.is_cuda:
+        raise ValueError("dm_mask must be a uint8 GPU tensor of the IF grid's shape")
+    if out is None:
+        out = torch.empty((n, 2 * wfs.n_valid), dtype=torch.float32, device=ifs.device)
+    s = wfs.struct()
+    a = _affine_struct(A)
+    if ws is None:
+        nb = C.c_size_t(0)
+        _check(lib.synim_im_repaired_workspace(C.byref(s), C.byref(a), C.byref(nb)),
+               "im_repaired_workspace")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=ifs.device)
+    _check(lib.synim_im_build_repaired(ifs.data_ptr(), n, H_in, W_in, dm_mask.data_ptr(),
+                                       float(threshold), C.byref(a), C.byref(s), out.data_ptr(),
+                                       ws.data_ptr(), ws.numel(), _stream_handle(ifs.device)),
+           "im_build_repaired")
+    return out
+
+
 def _dA_structs(dA):
     arr = (_abi.SynimAffine * 4)()
     for j in range(4):

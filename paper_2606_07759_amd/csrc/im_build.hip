@@ -65,6 +65,14 @@ struct PlanJob {
   int TX, TY, NSLOT, n_tiles_x;
   int n_tiles, BHmax;
   int H_in, W_in;             // IF grid, for the out-of-grid count (0: not counted)
+  // Edge repair of a pre-masked IF stack (Sec. 2.3), null dm_mask: none.
+  // The repaired phase of a subaperture's haloed samples reads core samples up
+  // to REPAIR_PAD pixels beyond its haloed window, so with repair on the
+  // sample window grows by that much on every side.
+  const uint8_t* dm_mask;     // [H_in][W_in] DM-side mask the IFs were multiplied by
+  double thresh;              // strict-core threshold on the interpolated mask
+  uint8_t* core;              // [(H+2)][(W+2)] strict core S over the haloed WFS window
+  double* ceff;               // [nv][RW*RW][2] effective (x, y) coefficient per sample
   int2* origin;
   int2* hrows;                // [nv] patch rows [x, y) holding a non-zero weight
   double* inv2nk;
@@ -82,6 +90,104 @@ template <bool TABLE>
 __device__ __forceinline__ const PlanJob& job_of(const PlanJob& one, const PlanJob* jobs) {
   if constexpr (TABLE) return jobs[blockIdx.y];
   else return one;
+}
+
+constexpr int REPAIR_PAD = 2;   // P1, P2 lie one and two pixels beyond an edge pixel
+
+// Sample window side of a subaperture: its haloed window, grown by REPAIR_PAD
+// on every side when the plan repairs edges.
+__host__ __device__ __forceinline__ int sample_window(int p, bool repair) {
+  return p + 2 + (repair ? 2 * REPAIR_PAD : 0);
+}
+
+// ---------------------------------------------------------------- edge repair
+// Step 1 (strict binarisation): S = {bilinear(M, A q + b) >= thresh} for every
+// haloed WFS sample q = (x, y), x in [-1, W], y in [-1, H]; M is zero outside
+// the IF grid.  Evaluated in FP64 with the plan's own source coordinates.
+__global__ __launch_bounds__(256) void plan_core_kernel(PlanJob J) {
+  const int W = J.n_sub_x * J.p, H = J.n_sub_y * J.p;
+  const int W2 = W + 2;
+  const long i = (long)blockIdx.x * 256 + threadIdx.x;
+  if (i >= (long)W2 * (H + 2)) return;
+  const int x = (int)(i % W2) - 1, y = (int)(i / W2) - 1;
+  const MapD m = J.m_dev ? *J.m_dev : J.m;
+  double xs, ys;
+  src_xy(m, x, y, xs, ys);
+  const double fi = floor(xs), fj = floor(ys);
+  const int ii = (int)fi, jj = (int)fj;
+  const double a = xs - fi, c = ys - fj;
+  auto Mv = [&](int u, int v) -> double {
+    return (u >= 0 && u < J.W_in && v >= 0 && v < J.H_in && J.dm_mask[(size_t)v * J.W_in + u])
+               ? 1.0 : 0.0;
+  };
+  const double mv = (1.0 - a) * (1.0 - c) * Mv(ii, jj) + a * (1.0 - c) * Mv(ii + 1, jj) +
+                    (1.0 - a) * c * Mv(ii, jj + 1) + a * c * Mv(ii + 1, jj + 1);
+  J.core[i] = mv >= J.thresh ? 1 : 0;
+}
+
+__device__ __forceinline__ int in_sub(const uint8_t* __restrict__ pupil, int W, int x0, int y0,
+                                      int p, int x, int y);
+
+// Steps 2 and 3 folded into the slope coefficients.  The repaired phase is
+// phi_r(q) = phi(q) on S, the mean of the extrapolations 2 phi(P1) - phi(P2)
+// or phi(P1) over the valid directions on the edge ring E = dilate(S) \ S
+// (cross dilation), and 0 elsewhere; it is linear in phi.  A subaperture's
+// slope sum_q c(q) phi_r(q) is therefore sum_q' c_eff(q') phi(q') with
+//   c_eff(q') = [q' in S] c(q') + sum_{e in E} c(e) R(e, q'),
+// R(e, e + d) = (2 if e + 2d in S else 1) / n_e and R(e, e + 2d) = -1 / n_e for
+// the directions d with e + d in S (n_e of them).  One thread per (valid
+// subaperture, sample of its grown window).
+__global__ __launch_bounds__(256) void plan_ceff_kernel(PlanJob J) {
+  const int p = J.p;
+  const int RW = sample_window(p, true);
+  const long gid = (long)blockIdx.x * 256 + threadIdx.x;
+  if (gid >= (long)J.nv * RW * RW) return;
+  const int kk = (int)(gid / (RW * RW));
+  const int e0 = (int)(gid - (long)kk * RW * RW);
+  const int k = J.valid[kk];
+  const int u = k % J.n_sub_x, v = k / J.n_sub_x;
+  const int W = J.n_sub_x * p, H = J.n_sub_y * p;
+  const int x0 = u * p, y0 = v * p;
+  const int qx = x0 - 1 - REPAIR_PAD + e0 % RW, qy = y0 - 1 - REPAIR_PAD + e0 / RW;
+  auto inS = [&](int x, int y) -> bool {
+    return x >= -1 && x <= W && y >= -1 && y <= H && J.core[(size_t)(y + 1) * (W + 2) + (x + 1)];
+  };
+  auto inWin = [&](int x, int y) -> bool { return x >= -1 && x <= W && y >= -1 && y <= H; };
+  auto cx = [&](int x, int y) {
+    return in_sub(J.pupil, W, x0, y0, p, x - 1, y) - in_sub(J.pupil, W, x0, y0, p, x + 1, y);
+  };
+  auto cy = [&](int x, int y) {
+    return in_sub(J.pupil, W, x0, y0, p, x, y - 1) - in_sub(J.pupil, W, x0, y0, p, x, y + 1);
+  };
+  const int DX[4] = {1, -1, 0, 0}, DY[4] = {0, 0, 1, -1};
+  double ex = 0.0, ey = 0.0;
+  if (inS(qx, qy)) {
+    ex = cx(qx, qy);
+    ey = cy(qx, qy);
+    // edge pixels e = q' - s d (s = 1, 2) whose extrapolation reads q'
+    for (int d = 0; d < 4; ++d)
+      for (int st = 1; st <= 2; ++st) {
+        const int ex_ = qx - st * DX[d], ey_ = qy - st * DY[d];
+        if (!inWin(ex_, ey_) || inS(ex_, ey_)) continue;
+        const int ccx = cx(ex_, ey_), ccy = cy(ex_, ey_);
+        if (ccx == 0 && ccy == 0) continue;
+        // e is on the ring iff some cross neighbour is in S; n_e counts them
+        int ne = 0;
+        for (int t = 0; t < 4; ++t) ne += inS(ex_ + DX[t], ey_ + DY[t]) ? 1 : 0;
+        if (ne == 0) continue;
+        double r = 0.0;
+        if (st == 1) {
+          r = inS(ex_ + 2 * DX[d], ey_ + 2 * DY[d]) ? 2.0 : 1.0;   // q' = P1 along d
+        } else {
+          if (!inS(ex_ + DX[d], ey_ + DY[d])) continue;            // q' = P2 needs P1
+          r = -1.0;
+        }
+        ex += ccx * r / ne;
+        ey += ccy * r / ne;
+      }
+  }
+  J.ceff[(size_t)gid * 2] = ex;
+  J.ceff[(size_t)gid * 2 + 1] = ey;
 }
 
 // Whether pixel (x, y) is a pupil pixel of the subaperture with corner (x0, y0).
@@ -113,11 +219,14 @@ __global__ __launch_bounds__(PLAN_SUBAPS_BLOCK) void plan_subaps_kernel(
   const int p = J.p;
   const int k = J.valid[kk];
   const int u = k % J.n_sub_x, v = k / J.n_sub_x;
-  const int W = J.n_sub_x * p;
+  const int W = J.n_sub_x * p, H = J.n_sub_y * p;
+  const bool repair = J.dm_mask != nullptr;
+  const int pad = repair ? REPAIR_PAD : 0;
   double xmin = 1e300, xmax = -1e300, ymin = 1e300, ymax = -1e300;
-  const int hw = p + 2;   // haloed window side
+  const int hw = sample_window(p, repair);   // (grown) haloed window side
   for (int i = lane; i < hw * hw; i += 64) {
-    const int y = v * p - 1 + i / hw, x = u * p - 1 + i % hw;
+    const int y = v * p - 1 - pad + i / hw, x = u * p - 1 - pad + i % hw;
+    if (x < -1 || x > W || y < -1 || y > H) continue;   // outside the WFS window
     double xs, ys;
     src_xy(m, x, y, xs, ys);
     xmin = fmin(xmin, xs);
@@ -138,14 +247,22 @@ __global__ __launch_bounds__(PLAN_SUBAPS_BLOCK) void plan_subaps_kernel(
   // samples this subaperture's central differences read (a non-zero c_x or
   // c_y) whose source point lies outside the IF grid: their bilinear taps
   // are zero-filled
+  // (with edge repair: a non-zero effective coefficient)
   int oob = 0;
   if (J.W_in > 0) {
     const int x0 = u * p, y0 = v * p;
     for (int i = lane; i < hw * hw; i += 64) {
-      const int y = y0 - 1 + i / hw, x = x0 - 1 + i % hw;
-      const int cx = in_sub(J.pupil, W, x0, y0, p, x - 1, y) - in_sub(J.pupil, W, x0, y0, p, x + 1, y);
-      const int cy = in_sub(J.pupil, W, x0, y0, p, x, y - 1) - in_sub(J.pupil, W, x0, y0, p, x, y + 1);
-      if (cx == 0 && cy == 0) continue;
+      const int y = y0 - 1 - pad + i / hw, x = x0 - 1 - pad + i % hw;
+      bool used;
+      if (repair) {
+        const double* ce = J.ceff + ((size_t)kk * hw * hw + i) * 2;
+        used = ce[0] != 0.0 || ce[1] != 0.0;
+      } else {
+        const int cx = in_sub(J.pupil, W, x0, y0, p, x - 1, y) - in_sub(J.pupil, W, x0, y0, p, x + 1, y);
+        const int cy = in_sub(J.pupil, W, x0, y0, p, x, y - 1) - in_sub(J.pupil, W, x0, y0, p, x, y + 1);
+        used = cx != 0 || cy != 0;
+      }
+      if (!used) continue;
       double xs, ys;
       src_xy(m, x, y, xs, ys);
       if (!(xs >= 0.0 && xs <= J.W_in - 1.0 && ys >= 0.0 && ys <= J.H_in - 1.0)) ++oob;
@@ -200,8 +317,14 @@ __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long 
   const double dx = (double)X - m.b0, dy = (double)Y - m.b1;
   const double qx = inv.a00 * dx + inv.a01 * dy;
   const double qy = inv.a10 * dx + inv.a11 * dy;
-  const int xl = max(u * p - 1, (int)ceil(qx - rx)), xh = min(u * p + p, (int)floor(qx + rx));
-  const int yl = max(v * p - 1, (int)ceil(qy - ry)), yh = min(v * p + p, (int)floor(qy + ry));
+  const bool repair = J.dm_mask != nullptr;
+  const int pad = repair ? REPAIR_PAD : 0;
+  const int RW = sample_window(p, repair);
+  const int H = J.n_sub_y * p;
+  const int xl = max(max(u * p - 1 - pad, -1), (int)ceil(qx - rx));
+  const int xh = min(min(u * p + p + pad, W), (int)floor(qx + rx));
+  const int yl = max(max(v * p - 1 - pad, -1), (int)ceil(qy - ry));
+  const int yh = min(min(v * p + p + pad, H), (int)floor(qy + ry));
   const int sx0 = u * p, sy0 = v * p;
   const int n_planes = MULTI ? J.n_planes : 1;
   Map4 dm{};
@@ -213,9 +336,17 @@ __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long 
   for (int j = 0; j < NP; ++j) acc[j][0] = acc[j][1] = 0.0;
   for (int y = yl; y <= yh; ++y)
     for (int x = xl; x <= xh; ++x) {
-      const int cx = in_sub(J.pupil, W, sx0, sy0, p, x - 1, y) - in_sub(J.pupil, W, sx0, sy0, p, x + 1, y);
-      const int cy = in_sub(J.pupil, W, sx0, sy0, p, x, y - 1) - in_sub(J.pupil, W, sx0, sy0, p, x, y + 1);
-      if (cx == 0 && cy == 0) continue;
+      double cx, cy;
+      if (repair) {
+        const double* ce =
+            J.ceff + ((size_t)kk * RW * RW + (y - (sy0 - 1 - pad)) * RW + (x - (sx0 - 1 - pad))) * 2;
+        cx = ce[0];
+        cy = ce[1];
+      } else {
+        cx = in_sub(J.pupil, W, sx0, sy0, p, x - 1, y) - in_sub(J.pupil, W, sx0, sy0, p, x + 1, y);
+        cy = in_sub(J.pupil, W, sx0, sy0, p, x, y - 1) - in_sub(J.pupil, W, sx0, sy0, p, x, y + 1);
+      }
+      if (cx == 0.0 && cy == 0.0) continue;
       double xs, ys;
       src_xy(m, x, y, xs, ys);
       const double fi = floor(xs), fj = floor(ys);
@@ -540,7 +671,7 @@ struct Dims {
 
 struct WsLayout {
   size_t status, counters, scratch, origin, hrows, inv2nk, weights, slot_kk, tile_info, rows,
-      partials, total;
+      partials, core, ceff, total;
 };
 
 constexpr int MAX_PLANES = 5;
@@ -574,10 +705,12 @@ void tile_bound(const synim_affine& A, int p, const Variant& v, int tx, int ty, 
 // Tile shapes of one variant for this geometry, cheapest first by the cost
 // model: staged IF floats per subaperture (a partial 128-byte line counted at
 // each row end), for tiles whose packed rows provably fit the stage buffers.
+// pe: the subaperture span the patches must cover (w.p; larger when the
+// plan repairs edges, whose sample window is wider).
 int tiles_for_variant(const synim_wfs& w, const synim_affine& A, const Variant& v, Dims* out,
-                      double* cost_out, int max_out) {
+                      double* cost_out, int max_out, int pe = -1) {
   int pw_need, ph_need;
-  patch_need(A, w.p, &pw_need, &ph_need);
+  patch_need(A, pe < 0 ? w.p : pe, &pw_need, &ph_need);
   if (v.PW < pw_need || v.PH() < ph_need) return 0;
   const int p = w.p;
   const long n_sub = (long)w.n_sub_x * w.n_sub_y;
@@ -631,9 +764,9 @@ int persistent_grid(StreamFn fn, int block);
 // many tiles as an XCD has resident workgroups (known only with a device
 // present).
 int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double* cost_out,
-                   int max_out) {
+                   int max_out, int pe = -1) {
   int pw_need, ph_need;
-  patch_need(A, w.p, &pw_need, &ph_need);
+  patch_need(A, pe < 0 ? w.p : pe, &pw_need, &ph_need);
   int best_area = INT_MAX;
   for (int i = 0; i < num_variants(); ++i)
     if (variants_table(nullptr)[i].PW >= pw_need && variants_table(nullptr)[i].PH() >= ph_need)
@@ -645,7 +778,7 @@ int candidate_dims(const synim_wfs& w, const synim_affine& A, Dims* out, double*
     if (v.PW * v.PH() != best_area) continue;
     Dims tmp[64];
     double tc[64];
-    const int m = tiles_for_variant(w, A, v, tmp, tc, 64);
+    const int m = tiles_for_variant(w, A, v, tmp, tc, 64, pe);
     const int G = persistent_grid(v.im4, v.BLOCK);
     for (int k = 0; k < m; ++k) {
       all.push_back({tc[k], tmp[k]});
@@ -720,10 +853,10 @@ TuneKey tune_key(const synim_wfs& w, const synim_affine& A) {
 
 // The tuned configuration for this geometry if there is one, else the
 // cost model's first choice.
-int choose_dims(const synim_wfs& w, const synim_affine& A, Dims* d) {
+int choose_dims(const synim_wfs& w, const synim_affine& A, Dims* d, int pe = -1) {
   Dims cand[MAX_CAND];
   double cost[MAX_CAND];
-  const int n = candidate_dims(w, A, cand, cost, MAX_CAND);
+  const int n = candidate_dims(w, A, cand, cost, MAX_CAND, pe);
   if (n == 0) return SYNIM_E_UNSUPPORTED;
   *d = cand[0];
   const TuneKey key = tune_key(w, A);
@@ -740,7 +873,7 @@ int choose_dims(const synim_wfs& w, const synim_affine& A, Dims* d) {
   return SYNIM_OK;
 }
 
-WsLayout layout(const synim_wfs& w, const Dims& d, int planes) {
+WsLayout layout(const synim_wfs& w, const Dims& d, int planes, bool repair = false) {
   WsLayout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -760,6 +893,9 @@ WsLayout layout(const synim_wfs& w, const Dims& d, int planes) {
   L.tile_info = take((size_t)d.n_tiles * sizeof(int4));
   L.rows = take((size_t)d.n_tiles * d.BHmax * sizeof(int2));
   L.partials = take(planes > 1 ? (size_t)4 * GMAX_VJP * sizeof(double) : 0);
+  const size_t rw = (size_t)sample_window(w.p, true);
+  L.core = take(repair ? (size_t)(w.n_sub_x * w.p + 2) * (w.n_sub_y * w.p + 2) : 0);
+  L.ceff = take(repair ? nv * rw * rw * 2 * sizeof(double) : 0);
   L.total = off;
   return L;
 }
@@ -779,16 +915,18 @@ struct Plan {
   int4* tile_info() const { return reinterpret_cast<int4*>(ws + L.tile_info); }
   int2* rows() const { return reinterpret_cast<int2*>(ws + L.rows); }
   double* partials() const { return reinterpret_cast<double*>(ws + L.partials); }
+  uint8_t* core() const { return reinterpret_cast<uint8_t*>(ws + L.core); }
+  double* ceff() const { return reinterpret_cast<double*>(ws + L.ceff); }
 };
 
 // Largest workspace any candidate configuration of this geometry needs, so a
 // workspace sized once stays valid whatever the autotuner picks later.
-size_t max_layout(const synim_wfs& w, const synim_affine& A, int planes) {
+size_t max_layout(const synim_wfs& w, const synim_affine& A, int planes, bool repair = false) {
   Dims cand[MAX_CAND];
   double cost[MAX_CAND];
-  const int n = candidate_dims(w, A, cand, cost, MAX_CAND);
+  const int n = candidate_dims(w, A, cand, cost, MAX_CAND, repair ? w.p + 2 * REPAIR_PAD : -1);
   size_t m = 0;
-  for (int i = 0; i < n; ++i) m = std::max(m, layout(w, cand[i], planes).total);
+  for (int i = 0; i < n; ++i) m = std::max(m, layout(w, cand[i], planes, repair).total);
   return m;
 }
 
@@ -863,6 +1001,18 @@ template <bool TABLE>
 int enqueue_plan_kernels(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv,
                          int max_e, int max_tiles, int planes, hipStream_t st,
                          bool tiles) {
+  if (!TABLE && one.dm_mask) {
+    // edge repair (single builds): strict core, then the effective coefficients
+    const long cells = (long)(one.n_sub_x * one.p + 2) * (one.n_sub_y * one.p + 2);
+    hipLaunchKernelGGL(plan_core_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, st,
+                       one);
+    SYNIM_HIP_TRY(hipGetLastError());
+    const int rw = sample_window(one.p, true);
+    const long thr = (long)one.nv * rw * rw;
+    hipLaunchKernelGGL(plan_ceff_kernel, dim3((unsigned)((thr + 255) / 256)), dim3(256), 0, st,
+                       one);
+    SYNIM_HIP_TRY(hipGetLastError());
+  }
   for (int j0 = 0; j0 < n; j0 += 65535) {
     const int nj = std::min(65535, n - j0);
     const PlanJob* jt = TABLE ? jobs_dev + j0 : nullptr;
@@ -1181,6 +1331,46 @@ extern "C" int synim_im_build(const float* ifs, int n_act, int H_in, int W_in,
   hipStream_t st = (hipStream_t)stream;
   Plan P{};
   rc = build_plan(*wfs, *A, nullptr, 1, H_in, W_in, ws, ws_bytes, st, &P);
+  if (rc != SYNIM_OK) return rc;
+  return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);
+}
+
+// ------------------------------------------------------- edge-repaired build
+extern "C" int synim_im_repaired_workspace(const synim_wfs* wfs, const synim_affine* A,
+                                           size_t* bytes) {
+  if (!wfs || !A || !bytes) return SYNIM_E_NULL;
+  int rc = validate_wfs(wfs);
+  if (rc != SYNIM_OK) return rc;
+  const size_t m = max_layout(*wfs, *A, 1, true);
+  if (m == 0) return SYNIM_E_UNSUPPORTED;
+  *bytes = m;
+  return SYNIM_OK;
+}
+
+extern "C" int synim_im_build_repaired(const float* ifs, int n_act, int H_in, int W_in,
+                                       const uint8_t* dm_mask, double threshold,
+                                       const synim_affine* A, const synim_wfs* wfs, float* im,
+                                       void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_common(ifs, n_act, H_in, W_in, A, wfs);
+  if (rc != SYNIM_OK) return rc;
+  if (!im || !dm_mask || !ws) return SYNIM_E_NULL;
+  if (!(threshold > 0.0 && threshold <= 1.0)) return SYNIM_E_PARAM;
+  hipStream_t st = (hipStream_t)stream;
+  Plan P{};
+  rc = choose_dims(*wfs, *A, &P.d, wfs->p + 2 * REPAIR_PAD);
+  if (rc != SYNIM_OK) return rc;
+  P.L = layout(*wfs, P.d, 1, true);
+  if (ws_bytes < P.L.total) return SYNIM_E_WORKSPACE;
+  P.ws = static_cast<char*>(ws);
+  const MapD m = to_map(*A);
+  const double det = m.a00 * m.a11 - m.a01 * m.a10;
+  if (!(std::fabs(det) > 1e-12)) return SYNIM_E_PARAM;
+  PlanJob J = make_job(*wfs, m, nullptr, Map4{}, nullptr, 1, P, H_in, W_in);
+  J.dm_mask = dm_mask;
+  J.thresh = threshold;
+  J.core = P.core();
+  J.ceff = P.ceff();
+  rc = enqueue_plans(J, nullptr, 1, J.nv, J.PH * J.PW, J.n_tiles, 1, st);
   if (rc != SYNIM_OK) return rc;
   return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);
 }
