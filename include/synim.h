@@ -168,6 +168,21 @@ int synim_im_workspace(const synim_wfs* wfs, const synim_affine* A, int planes, 
 int synim_im_build(const float* ifs, int n_act, int H_in, int W_in, const synim_affine* A,
                    const synim_wfs* wfs, float* im, void* ws, size_t ws_bytes, void* stream);
 
+/* Interaction matrix with the telescoping-sum slope engine, the G-tilt
+ * comparator of Sec. 2.2: the mean gradient over the pupil pixels of each
+ * valid subaperture k written as boundary differences,
+ *   s_x[k] = (1/n_k) sum over the rows of k, over the runs [xa, xb] of pupil
+ *            pixels of k on the row, of phi(xb + 1/2, y) - phi(xa - 1/2, y),
+ * and s_y likewise over columns, where every boundary value phi is ONE
+ * bilinear sample of the IF at the boundary point itself through the
+ * composite map (zero outside the IF grid).  Same arguments, layout and
+ * workspace (synim_im_workspace, planes = 1) as synim_im_build; the IF stack
+ * is streamed once through the same kernel.  The out-of-grid count of the
+ * plan is not kept (it is defined on the central-difference samples).
+ * Errors: as synim_im_build. */
+int synim_im_build_tsum(const float* ifs, int n_act, int H_in, int W_in, const synim_affine* A,
+                        const synim_wfs* wfs, float* im, void* ws, size_t ws_bytes, void* stream);
+
 /* Interaction matrix of a pre-masked IF stack with edge repair (Sec. 2.3).
  * The IFs were multiplied by a DM-side mask M on the IF grid, so the single
  * bilinear interpolation softens the mask edge and the warped phase collapses

@@ -202,6 +202,23 @@ def im_build(ifs, A, wfs: Wfs, out=None, ws=None):
     return out
 
 
+def im_build_tsum(ifs, A, wfs: Wfs, out=None, ws=None):
+    """IM with the telescoping-sum (G-tilt) slope engine (``synim_im_build_tsum``)."""
+    torch = _torch()
+    lib = load()
+    _dev_f32(ifs, "ifs")
+    n, H_in, W_in = ifs.shape
+    if out is None:
+        out = torch.empty((n, 2 * wfs.n_valid), dtype=torch.float32, device=ifs.device)
+    ws = _workspace(wfs, A, 1, ws, ifs.device)
+    s = wfs.struct()
+    a = _affine_struct(A)
+    _check(lib.synim_im_build_tsum(ifs.data_ptr(), n, H_in, W_in, C.byref(a), C.byref(s),
+                                   out.data_ptr(), ws.data_ptr(), ws.numel(),
+                                   _stream_handle(ifs.device)), "im_build_tsum")
+    return out
+
+
 def im_build_repaired(ifs, dm_mask, A, wfs: Wfs, threshold: float = 0.999999, out=None, ws=None):
     """IM of a pre-masked IF stack with the edge repair of Sec. 2.3 (see
     ``synim_im_build_repaired``); ``dm_mask`` is the DM-side 0/1 mask [H_in][W_in]."""

@@ -69,6 +69,8 @@ SIGNATURES = {
     "synim_sa_slopes": (I, [P, I, C.POINTER(SynimWfs), P, P]),
     "synim_im_workspace": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), I, C.POINTER(SZ)]),
     "synim_im_build": (I, [P, I, I, I, C.POINTER(SynimAffine), C.POINTER(SynimWfs), P, P, SZ, P]),
+    "synim_im_build_tsum": (I, [P, I, I, I, C.POINTER(SynimAffine), C.POINTER(SynimWfs), P, P,
+                                SZ, P]),
     "synim_im_repaired_workspace": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine),
                                         C.POINTER(SZ)]),
     "synim_im_build_repaired": (I, [P, I, I, I, P, C.c_double, C.POINTER(SynimAffine),

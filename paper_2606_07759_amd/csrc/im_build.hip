@@ -73,6 +73,7 @@ struct PlanJob {
   double thresh;              // strict-core threshold on the interpolated mask
   uint8_t* core;              // [(H+2)][(W+2)] strict core S over the haloed WFS window
   double* ceff;               // [nv][RW*RW][2] effective (x, y) coefficient per sample
+  int engine;                 // slope engine: ENGINE_CD or ENGINE_TSUM
   int2* origin;
   int2* hrows;                // [nv] patch rows [x, y) holding a non-zero weight
   double* inv2nk;
@@ -93,6 +94,11 @@ __device__ __forceinline__ const PlanJob& job_of(const PlanJob& one, const PlanJ
 }
 
 constexpr int REPAIR_PAD = 2;   // P1, P2 lie one and two pixels beyond an edge pixel
+
+// Slope engines (Sec. 2.2): central differences averaged over the pupil pixels,
+// or the G-tilt by telescoping sums, the phase difference across each pupil
+// run of a row (column) read at the run's two boundary points.
+constexpr int ENGINE_CD = 0, ENGINE_TSUM = 1;
 
 // Sample window side of a subaperture: its haloed window, grown by REPAIR_PAD
 // on every side when the plan repairs edges.
@@ -334,6 +340,34 @@ __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long 
   double acc[NP][2];
 #pragma unroll
   for (int j = 0; j < NP; ++j) acc[j][0] = acc[j][1] = 0.0;
+  if (!MULTI && J.engine == ENGINE_TSUM) {
+    // telescoping sums: boundary points (x + 1/2, y) with coefficient
+    // [x in k] - [x + 1 in k] for s_x, (x, y + 1/2) with [y in k] - [y + 1 in k]
+    // for s_y; each is one bilinear sample whose taps may include (X, Y)
+    for (int comp = 0; comp < 2; ++comp)
+      for (int a1 = 0; a1 < p; ++a1)          // row (s_x) or column (s_y) of k
+        for (int a2 = -1; a2 < p; ++a2) {     // position of the boundary along it
+          const int x = comp == 0 ? sx0 + a2 : sx0 + a1;
+          const int y = comp == 0 ? sy0 + a1 : sy0 + a2;
+          const int cc = comp == 0
+              ? in_sub(J.pupil, W, sx0, sy0, p, x, y) - in_sub(J.pupil, W, sx0, sy0, p, x + 1, y)
+              : in_sub(J.pupil, W, sx0, sy0, p, x, y) - in_sub(J.pupil, W, sx0, sy0, p, x, y + 1);
+          if (cc == 0) continue;
+          const double px = comp == 0 ? x + 0.5 : (double)x;
+          const double py = comp == 0 ? (double)y : y + 0.5;
+          const double xs = __fma_rn(m.a01, py, __fma_rn(m.a00, px, m.b0));
+          const double ys = __fma_rn(m.a11, py, __fma_rn(m.a10, px, m.b1));
+          const double fi = floor(xs), fj = floor(ys);
+          const double di = (double)X - fi, dj = (double)Y - fj;
+          if (!((di == 0.0 || di == 1.0) && (dj == 0.0 || dj == 1.0))) continue;
+          const double a = xs - fi, bb = ys - fj;
+          const double w = (di == 0.0 ? 1.0 - a : a) * (dj == 0.0 ? 1.0 - bb : bb);
+          acc[0][comp] += cc * w;
+        }
+    // the plan's scale is 1 / (2 n_k); the telescoping sum divides by n_k
+    acc[0][0] *= 2.0;
+    acc[0][1] *= 2.0;
+  } else
   for (int y = yl; y <= yh; ++y)
     for (int x = xl; x <= xh; ++x) {
       double cx, cy;
@@ -1331,6 +1365,31 @@ extern "C" int synim_im_build(const float* ifs, int n_act, int H_in, int W_in,
   hipStream_t st = (hipStream_t)stream;
   Plan P{};
   rc = build_plan(*wfs, *A, nullptr, 1, H_in, W_in, ws, ws_bytes, st, &P);
+  if (rc != SYNIM_OK) return rc;
+  return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);
+}
+
+// ------------------------------------------------- telescoping-sum engine
+extern "C" int synim_im_build_tsum(const float* ifs, int n_act, int H_in, int W_in,
+                                   const synim_affine* A, const synim_wfs* wfs, float* im,
+                                   void* ws, size_t ws_bytes, void* stream) {
+  int rc = check_common(ifs, n_act, H_in, W_in, A, wfs);
+  if (rc != SYNIM_OK) return rc;
+  if (!im || !ws) return SYNIM_E_NULL;
+  hipStream_t st = (hipStream_t)stream;
+  Plan P{};
+  rc = choose_dims(*wfs, *A, &P.d);
+  if (rc != SYNIM_OK) return rc;
+  P.L = layout(*wfs, P.d, 1);
+  if (ws_bytes < P.L.total) return SYNIM_E_WORKSPACE;
+  P.ws = static_cast<char*>(ws);
+  const MapD m = to_map(*A);
+  const double det = m.a00 * m.a11 - m.a01 * m.a10;
+  if (!(std::fabs(det) > 1e-12)) return SYNIM_E_PARAM;
+  // no out-of-grid count: it is defined on the central-difference samples
+  PlanJob J = make_job(*wfs, m, nullptr, Map4{}, nullptr, 1, P, 0, 0);
+  J.engine = ENGINE_TSUM;
+  rc = enqueue_plans(J, nullptr, 1, J.nv, J.PH * J.PW, J.n_tiles, 1, st);
   if (rc != SYNIM_OK) return rc;
   return launch_stream(P, ifs, n_act, H_in, W_in, wfs->n_valid, 0, 1, im, nullptr, st);
 }
