@@ -196,6 +196,73 @@ def mcao_leg(synim, dev, reps: int = 10):
             "config": cfg_b, "autotune_ms": tuned}
 
 
+def elt_engine_legs(synim, dev, cfg, Fd, A, wfs, launch_bytes, reps: int = 10):
+    """Two more builds of the ELT SCAO workload on its resident IF stack, plan
+    + stream per call: the telescoping-sum slope engine, and the edge-repaired
+    build of the same stack pre-masked (in place, so it runs last) by a DM-side
+    annulus 4 px inside the pupil's outer edge and 4 px outside its central
+    obscuration (the repair restores the samples the mask edge corrupts)."""
+    import torch
+    import workloads as wl
+    n_act = cfg.grid.n_act
+    ws = torch.empty(synim.im_workspace_bytes(wfs, A, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty((n_act, 2 * cfg.n_valid), dtype=torch.float32, device=dev)
+    ms_t = _event_ms(lambda: synim.im_build_tsum(Fd, A, wfs, out=out, ws=ws), reps)
+    M = wl.pupil_mask(512, 472.0, (0.28 * 480.0 + 8.0) / 472.0)
+    Md = torch.from_numpy(M).to(dev)
+    Fd.mul_(Md.to(torch.float32))
+    del ws
+    ms_r = _event_ms(lambda: synim.im_build_repaired(Fd, Md, A, wfs, out=out), reps)
+    return {"tsum": {"workload": "ELT SCAO IM, telescoping-sum slope engine (plan + stream)",
+                     "ms_per_build": ms_t, "columns_per_s": n_act / (ms_t * 1e-3),
+                     "frac_of_hbm_peak": launch_bytes / (ms_t * 1e-3) / 1e9 / PEAK_HBM_GBS},
+            "repair": {"workload": "ELT SCAO IM of the IF stack pre-masked by a DM-side annulus, "
+                                   "with edge repair (plan + stream)",
+                       "ms_per_build": ms_r, "columns_per_s": n_act / (ms_r * 1e-3),
+                       "frac_of_hbm_peak": launch_bytes / (ms_r * 1e-3) / 1e9 / PEAK_HBM_GBS}}
+
+
+def modal_leg(synim, dev, reps: int = 10):
+    """Modal IM under the full composite: 4519 Fourier modes (up to 38 cycles
+    per 480-px meta-pupil) on 512^2, one LGS WFS of the MCAO system (68x68
+    subapertures of 7 px, clocked 15 deg, anamorphic magnification 1.00 x 0.97)
+    at the 4-km DM's cone and footprint, the DM misregistered.  Plan + stream
+    per build; algorithmic bytes as the SCAO build's (touched IF pixels x
+    modes + the IM)."""
+    import torch
+    import workloads as wl
+    cfg = wl.mcao(0)
+    n_out = cfg.n_sub * cfg.p
+    g = cfg.pairs[4].geometry
+    g.wfs_mag_x, g.wfs_mag_y = 1.0, 0.97
+    g.dm_shift_x, g.dm_shift_y, g.dm_rot, g.dm_mag = 0.37, -0.23, math.radians(0.3), 1.003
+    modes = wl.fourier_modes(4519)
+    F = wl.fourier_stack_torch(modes, 512, 480.0, dev)
+    A = synim.affine_from_geometry(g, 512, 512, n_out, n_out)
+    P, v = cfg.pupils[1], cfg.valids[1]
+    wfs = synim.Wfs.from_numpy(P, cfg.p, v, device=dev)
+    ws = torch.empty(synim.im_workspace_bytes(wfs, A, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty((len(modes), 2 * len(v)), dtype=torch.float32, device=dev)
+    synim.im_autotune(F, A, wfs, max_candidates=16, ws=ws)
+
+    def step():
+        synim.im_plan(wfs, A, ws=ws, grid=(512, 512))
+        synim.im_apply(F, A, wfs, ws, out=out)
+    ms = _event_ms(step, reps)
+    S = int(touched_mask(P, cfg.p, v, A, 512).sum())
+    byts = (4 * S + 8 * len(v)) * len(modes)
+    del F
+    torch.cuda.empty_cache()
+    return {"workload": "modal IM: 4519 Fourier modes on 512^2, LGS WFS 68x68 x 7 px, composite "
+                        "map with cone, footprint, DM misregistration, WFS clocking and "
+                        "anamorphosis",
+            "ms_per_build": ms, "im_columns": len(modes),
+            "columns_per_s": len(modes) / (ms * 1e-3), "algorithmic_bytes": byts,
+            "achieved_GBs": byts / (ms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": byts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "config": synim.im_config(wfs, A)}
+
+
 def jacobian_leg(synim, dev, reps: int = 50):
     """Adjoint workload: 8x8 SCAO, 81 IFs; IM + 4 Jacobian planes, and the VJP."""
     import numpy as np
@@ -324,12 +391,17 @@ def main():
     apply_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     achieved = launch_bytes / (apply_ms * 1e-3) / 1e9
     traffic = stored_traffic(launch_bytes)
+    legs = {}
+    if not args.no_legs:
+        log("legs: telescoping-sum engine, edge repair")
+        legs.update(elt_engine_legs(synim, dev, cfg, Fd, A, wfs, launch_bytes))
     del Fd
     torch.cuda.empty_cache()
-    legs = {}
     if not args.no_legs:
         log("leg: MCAO batch")
         legs["mcao_batch"] = mcao_leg(synim, dev)
+        log("leg: modal IM")
+        legs["modal_im"] = modal_leg(synim, dev)
         log("leg: Jacobian / VJP")
         legs["adjoint"] = jacobian_leg(synim, dev)
         log("leg: learned misregistration vs Gauss-Newton")

@@ -35,6 +35,8 @@ __all__ = [
     "Geometry", "misreg_geometry", "ScaoConfig", "scao_small", "scao_elt",
     "McaoPair", "McaoConfig", "mcao", "zernike_noll", "probe_commands",
     "ProbeConfig", "probe_config", "draw_misreg_labels",
+    "FourierMode", "fourier_modes", "fourier_mode_values", "fourier_stack",
+    "fourier_stack_torch",
 ]
 
 # IF(pitch) = 0.15 * IF(0) for a Gaussian exp(-r^2 / 2 sigma^2).
@@ -412,3 +414,69 @@ def draw_misreg_labels(seed: int, p: int = 10):
     mag = rng.uniform(0.98, 1.02)
     snr = rng.uniform(20.0, 200.0)
     return np.array([tx, ty, rot, mag]), float(snr), rng
+
+
+# ------------------------------------------------------------ modal basis (Fourier)
+@dataclass
+class FourierMode:
+    """cos or sin of 2 pi (kx x + ky y) / period on the IF grid, about centre c."""
+    kx: int
+    ky: int
+    kind: int                   # 0: cos, 1: sin
+
+
+def fourier_modes(n_modes: int) -> List[FourierMode]:
+    """The first n_modes of a Fourier modal basis, ordered by spatial frequency:
+    frequency vectors (kx, ky) of the half plane (ky > 0, or ky = 0 and kx > 0),
+    by |k| then angle, each giving a cos and a sin mode.  The piston is left out.
+    A synthetic stand-in for the modal stacks (KL, Zernike, M4 modes) a DM can be
+    driven with: dense maps over the whole grid whose high orders carry the
+    spatial frequencies an interpolation filters."""
+    ks = []
+    r = 1
+    while len(ks) * 2 < n_modes:
+        ks = [(kx, ky) for ky in range(0, r + 1) for kx in range(-r, r + 1)
+              if (ky > 0 or kx > 0) and kx * kx + ky * ky <= r * r]
+        r += 1
+    ks.sort(key=lambda k: (k[0] * k[0] + k[1] * k[1], math.atan2(k[1], k[0])))
+    out = []
+    for kx, ky in ks:
+        out.append(FourierMode(kx, ky, 0))
+        out.append(FourierMode(kx, ky, 1))
+    return out[:n_modes]
+
+
+def fourier_mode_values(mode: FourierMode, x, y, period: float, cx: float, cy: float):
+    """The mode's exact value at arbitrary points (float64 arrays x, y)."""
+    ph = 2.0 * math.pi * (mode.kx * (np.asarray(x, np.float64) - cx) +
+                          mode.ky * (np.asarray(y, np.float64) - cy)) / period
+    return np.cos(ph) if mode.kind == 0 else np.sin(ph)
+
+
+def fourier_stack(modes: Sequence[FourierMode], grid_n: int, period: float) -> np.ndarray:
+    """float32 [M][grid_n][grid_n]: every mode at the IF pixel centres, about the
+    grid centre."""
+    c = (grid_n - 1) / 2.0
+    yy, xx = np.mgrid[0:grid_n, 0:grid_n].astype(np.float64)
+    return np.stack([fourier_mode_values(m, xx, yy, period, c, c) for m in modes]).astype(
+        np.float32)
+
+
+def fourier_stack_torch(modes: Sequence[FourierMode], grid_n: int, period: float, device,
+                        chunk: int = 256):
+    """fourier_stack built on a torch device in float64 chunks, rounded to float32."""
+    import torch
+    c = (grid_n - 1) / 2.0
+    t = torch.arange(grid_n, dtype=torch.float64, device=device) - c
+    kx = torch.tensor([m.kx for m in modes], dtype=torch.float64, device=device)
+    ky = torch.tensor([m.ky for m in modes], dtype=torch.float64, device=device)
+    kind = torch.tensor([m.kind for m in modes], dtype=torch.bool, device=device)
+    out = torch.empty((len(modes), grid_n, grid_n), dtype=torch.float32, device=device)
+    w = 2.0 * math.pi / period
+    for a0 in range(0, len(modes), chunk):
+        a1 = min(len(modes), a0 + chunk)
+        ph = w * (kx[a0:a1, None, None] * t[None, None, :] + ky[a0:a1, None, None] * t[None, :, None])
+        v = torch.where(kind[a0:a1, None, None], torch.sin(ph), torch.cos(ph))
+        out[a0:a1] = v.to(torch.float32)
+        del ph, v
+    return out
