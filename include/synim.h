@@ -412,6 +412,57 @@ int synim_batch_config(const synim_batch* b, int* out6);
 /* Release the handle (the workspace stays the caller's). */
 void synim_batch_destroy(synim_batch* b);
 
+/* ------------------------------------------------ tomographic projection
+ * P_opt = (P_DM^T P_DM + lambda I)^-1 P_DM^T P_Layer (Sec. 2.5, after Fusco et
+ * al.): the DM influence functions and the virtual layers' modes, each on its
+ * own grid at its conjugate altitude, sampled over the telescope pupil along
+ * every optimisation direction.  Pupil point r (metres from the axis, pupil
+ * pixel p_s metres, grid centre at (n-1)/2) reads a component of altitude h
+ * and pixel s at grid coordinate c + (r + h theta) / s by one bilinear
+ * interpolation (zero outside the grid).  With a binning factor b, a row is a
+ * b x b block of pupil pixels (kept if any pixel is in the mask): the mean of
+ * the samples at its pupil pixels.  Rows run direction-major, blocks
+ * row-major.  Everything is FP64; the products run on the FP64 matrix cores. */
+typedef struct {
+  const float* basis;          /* device [n][H][W] influence functions or modes */
+  int32_t n, H, W;
+  double altitude_m;           /* conjugate altitude (m)                        */
+  double pixel_m;              /* grid pixel size (m)                            */
+} synim_proj_component;
+
+/* Rows of the projection matrices: kept blocks x n_dir (pupil host [Hp][Wp]). */
+int synim_proj_rows(const uint8_t* pupil, int Hp, int Wp, int bin, int n_dir, int* n_rows);
+/* Workspace bytes of synim_proj_opt (layers may be NULL for synim_proj_matrix). */
+int synim_proj_workspace(const synim_proj_component* dms, int n_dm,
+                         const synim_proj_component* layers, int n_layer, int n_dir,
+                         const uint8_t* pupil, int Hp, int Wp, int bin, size_t* bytes);
+/* The projection matrix of components comps (columns in component order),
+ * stored transposed: Pt (device float64) [sum n][ld], Pt[col][row], ld >= rows.
+ * dirs (host) [n_dir][2] radians; pupil (host) [Hp][Wp] 0/1.  Synchronises.
+ * Errors: SYNIM_E_NULL, SYNIM_E_SHAPE (Hp, Wp not multiples of bin, ld),
+ *         SYNIM_E_PARAM, SYNIM_E_WORKSPACE, SYNIM_E_HIP. */
+int synim_proj_matrix(const synim_proj_component* comps, int n_comp, const double* dirs, int n_dir,
+                      const uint8_t* pupil, int Hp, int Wp, double pupil_pixel_m, int bin,
+                      double* Pt, long ld, void* ws, size_t ws_bytes, void* stream);
+/* P_opt (device float64 [sum n_dm][sum n_layer], row-major).  lambda >= 0.
+ * Synchronises.  Errors: as synim_proj_matrix; SYNIM_E_PARAM also when
+ * P_DM^T P_DM + lambda I is not positive definite. */
+int synim_proj_opt(const synim_proj_component* dms, int n_dm, const synim_proj_component* layers,
+                   int n_layer, const double* dirs, int n_dir, const uint8_t* pupil, int Hp,
+                   int Wp, double pupil_pixel_m, int bin, double lambda, double* popt, void* ws,
+                   size_t ws_bytes, void* stream);
+/* Building blocks (device float64, row-major):
+ *   C[m][n] = alpha sum_k X(k, m) Y(k, n) + beta C[m][n], X(k, m) = X[k sxk + m sxm],
+ *   Y(k, n) = Y[k syk + n syn] (any strides; FP64 MFMA tiles);
+ *   lower Cholesky of the lower triangle of A [n][ld] in place (*status
+ *   (device int) gets bit 0 when a pivot is not positive; zero it first);
+ *   B [n][ldb] <- (L L^T)^-1 B for m right-hand sides. */
+int synim_gemm_f64(int M, int N, int K, double alpha, const double* X, long sxk, long sxm,
+                   const double* Y, long syk, long syn, double beta, double* C, long ldc,
+                   void* stream);
+int synim_potrf_f64(double* A, int n, long ld, int* status, void* stream);
+int synim_potrs_f64(const double* L, int n, long ld, double* B, int m, long ldb, void* stream);
+
 /* --------------------------------------------------- learned estimator
  * A small MLP x (n_in) -> h1 -> h2 -> n_out (ReLU after the hidden layers),
  * trained with an MSE loss and Adam, for the learned misregistration

@@ -400,6 +400,108 @@ def plan_oob(ws) -> int:
     return int(v.value)
 
 
+# ------------------------------------------------------ tomographic projection
+def _proj_components(comps):
+    """comps: list of (basis GPU float32 [n][H][W], altitude m, pixel m)."""
+    arr = (_abi.SynimProjComponent * len(comps))()
+    for i, (F, h, s) in enumerate(comps):
+        _dev_f32(F, "basis")
+        n, H, W = F.shape
+        arr[i] = _abi.SynimProjComponent(F.data_ptr(), n, H, W, float(h), float(s))
+    return arr
+
+
+def _host_u8(a):
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.uint8))
+    return a, a.ctypes.data_as(C.c_void_p)
+
+
+def proj_matrix(comps, dirs, pupil, pupil_pixel_m: float, bin: int = 1):
+    """Transposed projection matrix Pt [sum n][rows] (GPU float64) of the components
+    over the pupil (host 0/1 array) along every direction (radians, [n_dir][2])."""
+    torch = _torch()
+    lib = load()
+    arr = _proj_components(comps)
+    pu, pp = _host_u8(pupil)
+    Hp, Wp = pu.shape
+    d = np.ascontiguousarray(np.asarray(dirs, np.float64).reshape(-1, 2))
+    rows = C.c_int(0)
+    _check(lib.synim_proj_rows(pp, Hp, Wp, bin, d.shape[0], C.byref(rows)), "proj_rows")
+    nb = C.c_size_t(0)
+    _check(lib.synim_proj_workspace(arr, len(comps), None, 0, d.shape[0], pp, Hp, Wp, bin,
+                                    C.byref(nb)), "proj_workspace")
+    dev = comps[0][0].device
+    ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    ncol = sum(int(F.shape[0]) for F, _, _ in comps)
+    Pt = torch.empty((ncol, rows.value), dtype=torch.float64, device=dev)
+    _check(lib.synim_proj_matrix(arr, len(comps), d.ctypes.data_as(C.c_void_p), d.shape[0], pp,
+                                 Hp, Wp, float(pupil_pixel_m), bin, Pt.data_ptr(), rows.value,
+                                 ws.data_ptr(), ws.numel(), _stream_handle(dev)), "proj_matrix")
+    return Pt
+
+
+def proj_opt(dms, layers, dirs, pupil, pupil_pixel_m: float, lam: float, bin: int = 1,
+             ws=None):
+    """P_opt [sum n_dm][sum n_layer] (GPU float64) of Sec. 2.5."""
+    torch = _torch()
+    lib = load()
+    a_dm, a_l = _proj_components(dms), _proj_components(layers)
+    pu, pp = _host_u8(pupil)
+    Hp, Wp = pu.shape
+    d = np.ascontiguousarray(np.asarray(dirs, np.float64).reshape(-1, 2))
+    dev = dms[0][0].device
+    if ws is None:
+        nb = C.c_size_t(0)
+        _check(lib.synim_proj_workspace(a_dm, len(dms), a_l, len(layers), d.shape[0], pp, Hp, Wp,
+                                        bin, C.byref(nb)), "proj_workspace")
+        ws = torch.empty(nb.value, dtype=torch.uint8, device=dev)
+    ndm = sum(int(F.shape[0]) for F, _, _ in dms)
+    nl = sum(int(F.shape[0]) for F, _, _ in layers)
+    out = torch.empty((ndm, nl), dtype=torch.float64, device=dev)
+    _check(lib.synim_proj_opt(a_dm, len(dms), a_l, len(layers), d.ctypes.data_as(C.c_void_p),
+                              d.shape[0], pp, Hp, Wp, float(pupil_pixel_m), bin, float(lam),
+                              out.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(dev)),
+           "proj_opt")
+    return out
+
+
+def proj_workspace_bytes(dms, layers, n_dir: int, pupil, bin: int = 1) -> int:
+    lib = load()
+    a_dm, a_l = _proj_components(dms), _proj_components(layers)
+    pu, pp = _host_u8(pupil)
+    nb = C.c_size_t(0)
+    _check(lib.synim_proj_workspace(a_dm, len(dms), a_l, len(layers), n_dir, pp, pu.shape[0],
+                                    pu.shape[1], bin, C.byref(nb)), "proj_workspace")
+    return int(nb.value)
+
+
+def gemm_f64(M, N, K, alpha, X, sxk, sxm, Y, syk, syn, beta, Cm, ldc):
+    """C[m][n] = alpha sum_k X(k,m) Y(k,n) + beta C[m][n] on GPU float64 tensors (strides
+    in elements)."""
+    lib = load()
+    _check(lib.synim_gemm_f64(M, N, K, float(alpha), X.data_ptr(), sxk, sxm, Y.data_ptr(), syk,
+                              syn, float(beta), Cm.data_ptr(), ldc, _stream_handle(Cm.device)),
+           "gemm_f64")
+    return Cm
+
+
+def potrf_f64(A, status):
+    """In-place lower Cholesky of the GPU float64 square matrix A; status int32 GPU [1]."""
+    lib = load()
+    n = A.shape[0]
+    _check(lib.synim_potrf_f64(A.data_ptr(), n, A.stride(0), status.data_ptr(),
+                               _stream_handle(A.device)), "potrf_f64")
+    return A
+
+
+def potrs_f64(L, B):
+    """B <- (L L^T)^-1 B in place (GPU float64, row-major)."""
+    lib = load()
+    _check(lib.synim_potrs_f64(L.data_ptr(), L.shape[0], L.stride(0), B.data_ptr(), B.shape[1],
+                               B.stride(0), _stream_handle(B.device)), "potrs_f64")
+    return B
+
+
 # --------------------------------------------------------------- multi-pair
 class Batch:
     """Every (WFS, DM) pair of a multi-WFS system built in one persistent launch.

@@ -38,6 +38,11 @@ class SynimPair(C.Structure):
     _fields_ = [("wfs", C.c_int32), ("dm", C.c_int32), ("A", SynimAffine), ("im", C.c_void_p)]
 
 
+class SynimProjComponent(C.Structure):
+    _fields_ = [("basis", C.c_void_p), ("n", C.c_int32), ("H", C.c_int32), ("W", C.c_int32),
+                ("altitude_m", C.c_double), ("pixel_m", C.c_double)]
+
+
 class SynimMlp(C.Structure):
     _fields_ = [(n, C.c_int32) for n in ("n_in", "h1", "h2", "n_out", "seg0", "len0", "seg1",
                                          "len1")]
@@ -103,6 +108,17 @@ SIGNATURES = {
     "synim_batch_autotune": (I, [P, I, C.POINTER(C.c_float), C.POINTER(I), P]),
     "synim_batch_config": (I, [P, C.POINTER(I)]),
     "synim_batch_destroy": (None, [P]),
+    "synim_proj_rows": (I, [P, I, I, I, I, C.POINTER(I)]),
+    "synim_proj_workspace": (I, [C.POINTER(SynimProjComponent), I, C.POINTER(SynimProjComponent),
+                                 I, I, P, I, I, I, C.POINTER(SZ)]),
+    "synim_proj_matrix": (I, [C.POINTER(SynimProjComponent), I, P, I, P, I, I, C.c_double, I, P,
+                              C.c_long, P, SZ, P]),
+    "synim_proj_opt": (I, [C.POINTER(SynimProjComponent), I, C.POINTER(SynimProjComponent), I, P,
+                           I, P, I, I, C.c_double, I, C.c_double, P, P, SZ, P]),
+    "synim_gemm_f64": (I, [I, I, I, C.c_double, P, C.c_long, C.c_long, P, C.c_long, C.c_long,
+                           C.c_double, P, C.c_long, P]),
+    "synim_potrf_f64": (I, [P, I, C.c_long, P, P]),
+    "synim_potrs_f64": (I, [P, I, C.c_long, P, I, C.c_long, P]),
     "synim_mlp_param_count": (SZ, [C.POINTER(SynimMlp)]),
     "synim_mlp_scratch_floats": (SZ, [C.POINTER(SynimMlp), I]),
     "synim_mlp_forward": (I, [C.POINTER(SynimMlp), P, P, I, P, P, P]),
