@@ -263,6 +263,49 @@ def modal_leg(synim, dev, reps: int = 10):
             "config": synim.im_config(wfs, A)}
 
 
+PEAK_F64_MFMA_TFS = 78.6
+
+
+def projection_leg(synim, dev):
+    """Tomographic projection P_opt (Sec. 2.5) at the MCAO scale: the 3 DMs
+    (8171 IFs on 512^2 at 8.19 cm/px) and 3 virtual layers (2, 8, 16 km; 4083
+    Gaussian modes) over 9 directions (3x3 grid, 40 arcsec pitch), the 476-px
+    pupil binned 4x4 (94 104 rows).  The dominant kernel is the FP64 MFMA GEMM
+    of the Gram matrix (timed alone on the full square: 2 rows n^2 flops)."""
+    import numpy as np
+    import torch
+    import workloads as wl
+    cfg = wl.mcao(0)
+    pix = cfg.pixel_scale_m
+    dms = [(wl.if_stack_torch(g, dev), h, pix) for g, h in zip(cfg.grids, cfg.altitudes_m)]
+    lgrids = [wl.actuator_grid(41, 12.0, 512, keep_radius=250.0) for _ in range(3)]
+    layers = [(wl.if_stack_torch(g, dev), h, pix) for g, h in zip(lgrids, (2000.0, 8000.0,
+                                                                          16000.0))]
+    a = math.radians(40.0 / 3600.0)
+    dirs = np.array([[x * a, y * a] for y in (-1, 0, 1) for x in (-1, 0, 1)])
+    pupil = wl.pupil_mask(476, 476.0, 0.28)
+    Pt = synim.proj_matrix(dms, dirs, pupil, pix, bin=4)
+    n, rows = Pt.shape
+    G = torch.empty((n, n), dtype=torch.float64, device=dev)
+    gemm_ms = _event_ms(lambda: synim.gemm_f64(n, n, rows, 1.0, Pt, 1, rows, Pt, 1, rows, 0.0,
+                                               G, n), 2)
+    lam = float((Pt * Pt).sum(dim=1).mean()) * 1e-3
+    del G, Pt
+    torch.cuda.empty_cache()
+    ws = torch.empty(synim.proj_workspace_bytes(dms, layers, len(dirs), pupil, 4),
+                     dtype=torch.uint8, device=dev)
+    opt_ms = _event_ms(lambda: synim.proj_opt(dms, layers, dirs, pupil, pix, lam, bin=4, ws=ws), 2)
+    flops = 2.0 * rows * n * n
+    del ws, dms, layers
+    torch.cuda.empty_cache()
+    return {"workload": "P_opt: 3 DMs (8171 IFs) x 3 layers (4083 modes), 9 directions, 476-px "
+                        "pupil binned 4x4 (94104 rows), FP64",
+            "p_opt_ms": opt_ms, "gram_gemm_ms": gemm_ms, "gram_gemm_flops": flops,
+            "roofline": {"bound": "mfma", "achieved": flops / (gemm_ms * 1e-3) / 1e12,
+                         "peak": PEAK_F64_MFMA_TFS, "unit": "TFLOP/s",
+                         "frac": flops / (gemm_ms * 1e-3) / 1e12 / PEAK_F64_MFMA_TFS}}
+
+
 def jacobian_leg(synim, dev, reps: int = 50):
     """Adjoint workload: 8x8 SCAO, 81 IFs; IM + 4 Jacobian planes, and the VJP."""
     import numpy as np
@@ -402,6 +445,8 @@ def main():
         legs["mcao_batch"] = mcao_leg(synim, dev)
         log("leg: modal IM")
         legs["modal_im"] = modal_leg(synim, dev)
+        log("leg: tomographic projection")
+        legs["projection"] = projection_leg(synim, dev)
         log("leg: Jacobian / VJP")
         legs["adjoint"] = jacobian_leg(synim, dev)
         log("leg: learned misregistration vs Gauss-Newton")

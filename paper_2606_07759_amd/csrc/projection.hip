@@ -74,12 +74,14 @@ __global__ __launch_bounds__(256) void proj_sample_kernel(SampleArgs g) {
 // ---------------------------------------------------------------- FP64 GEMM
 // C[m][n] = alpha sum_k X(k, m) Y(k, n) + beta C[m][n], X(k, m) = X[k sxk + m sxm],
 // Y(k, n) = Y[k syk + n syn], C row-major with ldc.  One workgroup of 256
-// threads per 64x64 tile of C; each wave owns a 32x32 quarter as 2x2 blocks
+// threads per 128x128 tile of C; each wave owns a 64x64 quarter as 4x4 blocks
 // of v_mfma_f64_16x16x4f64 (lane l feeds A[l%16][l/16] and B[l/16][l%16]
-// and holds D[4r + l/16][l%16], r = 0..3).  K advances in chunks of 16
-// staged in LDS.  lower: only tiles with some m >= n (a symmetric result's
-// lower triangle) are computed.
-constexpr int GT = 64, GK = 16, GPAD = 2;
+// and holds D[4r + l/16][l%16], r = 0..3).  K advances in chunks of 16 through
+// two LDS buffers: the next chunk's global loads are in flight while the
+// current one feeds the matrix cores.  lower: only tiles with some m >= n (a
+// symmetric result's lower triangle) are computed.
+constexpr int GT = 128, GK = 16, GPAD = 2;
+constexpr int GLOADS = GK * GT / 256;   // elements of one operand chunk per thread
 
 struct GemmArgs {
   int M, N, K;
@@ -93,67 +95,97 @@ struct GemmArgs {
   int lower;
 };
 
-__device__ __forceinline__ void gemm_stage(const double* P, long sk, long sm, int k0, int m0,
-                                           int K, int M, double (*S)[GT + GPAD], int tid) {
-  // 16 x 64 tile: 1024 elements, 4 per thread, read along the unit stride
+// (kk, mm) of element q of this thread in a 16 x 128 chunk, reading along the
+// operand's unit stride
+__device__ __forceinline__ void gemm_elem(long sk, int tid, int q, int& kk, int& mm) {
+  const int e = tid + 256 * q;
+  if (sk == 1) {
+    kk = e % GK;
+    mm = e / GK;
+  } else {
+    kk = e / GT;
+    mm = e % GT;
+  }
+}
+
+__device__ __forceinline__ void gemm_fetch(const double* P, long sk, long sm, int k0, int m0,
+                                           int K, int M, int tid, double (&r)[GLOADS]) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int e = tid + 256 * q;
+  for (int q = 0; q < GLOADS; ++q) {
     int kk, mm;
-    if (sk == 1) {
-      kk = e % GK;
-      mm = e / GK;
-    } else {
-      kk = e / GT;
-      mm = e % GT;
-    }
+    gemm_elem(sk, tid, q, kk, mm);
     const int k = k0 + kk, m = m0 + mm;
-    S[kk][mm] = (k < K && m < M) ? P[(long)k * sk + (long)m * sm] : 0.0;
+    r[q] = (k < K && m < M) ? P[(long)k * sk + (long)m * sm] : 0.0;
+  }
+}
+
+__device__ __forceinline__ void gemm_put(long sk, int tid, const double (&r)[GLOADS],
+                                         double (*S)[GT + GPAD]) {
+#pragma unroll
+  for (int q = 0; q < GLOADS; ++q) {
+    int kk, mm;
+    gemm_elem(sk, tid, q, kk, mm);
+    S[kk][mm] = r[q];
   }
 }
 
 __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
   if (g.lower && m0 + GT - 1 < n0) return;   // tile wholly above the diagonal
-  __shared__ double Xs[GK][GT + GPAD], Ys[GK][GT + GPAD];
+  __shared__ double Xs[2][GK][GT + GPAD], Ys[2][GK][GT + GPAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
-  d4 acc[2][2];
+  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+  d4 acc[4][4];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  for (int k0 = 0; k0 < g.K; k0 += GK) {
-    __syncthreads();
-    gemm_stage(g.X, g.sxk, g.sxm, k0, m0, g.K, g.M, Xs, tid);
-    gemm_stage(g.Y, g.syk, g.syn, k0, n0, g.K, g.N, Ys, tid);
-    __syncthreads();
+    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  double rx[GLOADS], ry[GLOADS];
+  gemm_fetch(g.X, g.sxk, g.sxm, 0, m0, g.K, g.M, tid, rx);
+  gemm_fetch(g.Y, g.syk, g.syn, 0, n0, g.K, g.N, tid, ry);
+  gemm_put(g.sxk, tid, rx, Xs[0]);
+  gemm_put(g.syk, tid, ry, Ys[0]);
+  __syncthreads();
+  const int nk = (g.K + GK - 1) / GK;
+  for (int c = 0; c < nk; ++c) {
+    const int buf = c & 1;
+    const bool more = c + 1 < nk;
+    if (more) {
+      gemm_fetch(g.X, g.sxk, g.sxm, (c + 1) * GK, m0, g.K, g.M, tid, rx);
+      gemm_fetch(g.Y, g.syk, g.syn, (c + 1) * GK, n0, g.K, g.N, tid, ry);
+    }
 #pragma unroll
     for (int s = 0; s < GK / 4; ++s) {
       const int kr = 4 * s + (lane >> 4);
-      double a[2], b[2];
+      double a[4], b[4];
 #pragma unroll
-      for (int i = 0; i < 2; ++i) a[i] = Xs[kr][wm + 16 * i + (lane & 15)];
+      for (int i = 0; i < 4; ++i) a[i] = Xs[buf][kr][wm + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 2; ++j) b[j] = Ys[kr][wn + 16 * j + (lane & 15)];
+      for (int j = 0; j < 4; ++j) b[j] = Ys[buf][kr][wn + 16 * j + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j)
+        for (int j = 0; j < 4; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
+    if (more) {
+      // the other buffer was last read in iteration c - 1, before its closing barrier
+      gemm_put(g.sxk, tid, rx, Xs[buf ^ 1]);
+      gemm_put(g.syk, tid, ry, Ys[buf ^ 1]);
+    }
+    __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j)
+    for (int j = 0; j < 4; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + 16 * i + 4 * r + (lane >> 4);
         const int n = n0 + wn + 16 * j + (lane & 15);
         if (m < g.M && n < g.N && (!g.lower || m >= n)) {
-          double* c = g.C + (long)m * g.ldc + n;
-          *c = g.alpha * acc[i][j][r] + (g.beta == 0.0 ? 0.0 : g.beta * *c);
+          double* cp = g.C + (long)m * g.ldc + n;
+          *cp = g.alpha * acc[i][j][r] + (g.beta == 0.0 ? 0.0 : g.beta * *cp);
         }
       }
 }
