@@ -104,11 +104,22 @@ def cpu_baseline(seed: int, target_s: float):
         ncpu = len(os.sched_getaffinity(0))
     except AttributeError:
         ncpu = os.cpu_count() or 1
+    # one GPU's share of the host is 16 CPUs on the GPU machines: more worker
+    # processes than that would take cores the GPU's own host work needs
     workers = max(1, min(16, ncpu))
     chunk = 4
-    # calibrate on one chunk in-process
+    # calibrate on one chunk in-process: the one-core rate
     t1 = _oracle_chunk((seed, list(range(chunk))))
     per_col = t1 / chunk
+    cpu_model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     n_cols = int(max(workers * chunk, min(5257, target_s * workers / per_col)))
     n_cols = min(5256, (n_cols + chunk - 1) // chunk * chunk)
     cols = np.linspace(0, 5256, n_cols).astype(int).tolist()
@@ -121,7 +132,10 @@ def cpu_baseline(seed: int, target_s: float):
     wall = time.perf_counter() - t0
     return {"value": n_cols / wall, "unit": "IM columns/s", "cores": workers, "kind": "oracle",
             "sample": f"{n_cols} of 5257 IM columns of the ELT workload (seed {seed}), FP64 "
-                      f"NumPy oracle, {workers} worker processes, {wall:.1f} s wall"}
+                      f"NumPy oracle, {workers} worker processes, {wall:.1f} s wall",
+            "one_core_value": 1.0 / per_col, "cpu_model": cpu_model,
+            "host_cpus": os.cpu_count(), "affinity_cpus": ncpu,
+            "workers_note": "worker processes capped at 16, one GPU's share of the host CPUs"}
 
 
 def stored_traffic(n_launch_bytes):
