@@ -236,6 +236,41 @@ def elt_engine_legs(synim, dev, cfg, Fd, A, wfs, launch_bytes, reps: int = 10):
                        "frac_of_hbm_peak": launch_bytes / (ms_r * 1e-3) / 1e9 / PEAK_HBM_GBS}}
 
 
+def standalone_legs(synim, dev, cfg, Fd, A, wfs, reps: int = 5):
+    """The two standalone steps on the ELT stack: the warp of every IF onto the
+    haloed 482^2 WFS window (reads the source pixels the window's bilinear
+    taps touch, writes the window), then the slopes of the warped stack
+    (reads every haloed sample, writes the IM).  Algorithmic bytes from the
+    geometry; HIP events."""
+    import numpy as np
+    import torch
+    n_act, H = cfg.grid.n_act, cfg.n_out
+    Hh = H + 2
+    warped = torch.empty((n_act, Hh, Hh), dtype=torch.float32, device=dev)
+    ms_w = _event_ms(lambda: synim.affine_warp(Fd, A, H, H, halo=1, out=warped), reps)
+    ys, xs = np.mgrid[-1:H + 1, -1:H + 1].astype(np.float64)
+    sx = A[0, 0] * xs + A[0, 1] * ys + A[0, 2]
+    sy = A[1, 0] * xs + A[1, 1] * ys + A[1, 2]
+    i, j = np.floor(sx).astype(np.int64), np.floor(sy).astype(np.int64)
+    T = np.zeros((512, 512), bool)
+    for di in (0, 1):
+        for dj in (0, 1):
+            ok = (i + di >= 0) & (i + di < 512) & (j + dj >= 0) & (j + dj < 512)
+            T[(j + dj)[ok], (i + di)[ok]] = True
+    wb = (4 * int(T.sum()) + 4 * Hh * Hh) * n_act
+    out = torch.empty((n_act, 2 * cfg.n_valid), dtype=torch.float32, device=dev)
+    ms_s = _event_ms(lambda: synim.sa_slopes(warped, wfs, out=out), reps)
+    sb = (4 * Hh * Hh + 8 * cfg.n_valid) * n_act
+    del warped
+    torch.cuda.empty_cache()
+    return {"warp": {"workload": "synim_affine_warp: 5257 ELT IFs onto the haloed 482^2 window",
+                     "ms": ms_w, "algorithmic_bytes": wb,
+                     "frac_of_hbm_peak": wb / (ms_w * 1e-3) / 1e9 / PEAK_HBM_GBS},
+            "slopes": {"workload": "synim_sa_slopes: 5257 warped 482^2 maps -> the ELT IM",
+                       "ms": ms_s, "algorithmic_bytes": sb,
+                       "frac_of_hbm_peak": sb / (ms_s * 1e-3) / 1e9 / PEAK_HBM_GBS}}
+
+
 def modal_leg(synim, dev, reps: int = 10):
     """Modal IM under the full composite: 4519 Fourier modes (up to 38 cycles
     per 480-px meta-pupil) on 512^2, one LGS WFS of the MCAO system (68x68
@@ -450,6 +485,8 @@ def main():
     traffic = stored_traffic(launch_bytes)
     legs = {}
     if not args.no_legs:
+        log("legs: standalone warp and slopes")
+        legs.update(standalone_legs(synim, dev, cfg, Fd, A, wfs))
         log("legs: telescoping-sum engine, edge repair")
         legs.update(elt_engine_legs(synim, dev, cfg, Fd, A, wfs, launch_bytes))
     del Fd
