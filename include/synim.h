@@ -144,7 +144,8 @@ int synim_affine_warp(const float* ifs, int n, int H_in, int W_in, const synim_a
  *   phase  device float32 [n][H+2][W+2] with pixel (x, y) at [y+1][x+1],
  *          H = n_sub_y*p, W = n_sub_x*p
  *   slopes device float32 [n][2N]
- * Errors: SYNIM_E_NULL, SYNIM_E_SHAPE, SYNIM_E_HIP. */
+ * A listed subaperture with no pupil pixel reads 0 in both components.
+ * Errors: SYNIM_E_NULL, SYNIM_E_SHAPE (also p > 256), SYNIM_E_HIP. */
 int synim_sa_slopes(const float* phase, int n, const synim_wfs* wfs, float* slopes, void* stream);
 
 /* ------------------------------------------------------------ fused build */

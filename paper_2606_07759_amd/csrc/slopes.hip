@@ -5,49 +5,74 @@
 namespace synim {
 namespace {
 
-constexpr int WAVES = 4;
+constexpr int SBLOCK = 256;   // pixel columns of one workgroup
 
-__device__ __forceinline__ float wave_sum(float v) {
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
-
-// One wave per (valid subaperture, phase map).  Lanes walk the p*p pixels in a
-// fixed order and the butterfly reduction is fixed, so results are
-// bit-reproducible from run to run.
-__global__ __launch_bounds__(64 * WAVES) void slopes_kernel(const float* __restrict__ phase,
-                                                            const int32_t* __restrict__ valid,
-                                                            const uint8_t* __restrict__ pupil,
-                                                            int n_sub_x, int n_sub_y, int p,
-                                                            int nv, float* __restrict__ slopes) {
-  const int lane = threadIdx.x & 63;
-  const int kk = blockIdx.x * WAVES + (threadIdx.x >> 6);
+// One workgroup per (phase map, subaperture row, run of whole subapertures
+// across SBLOCK pixel columns).  Thread t owns pixel column x = x0 + t: it
+// reads, row by row, the four neighbours its central differences need
+// (consecutive threads read consecutive columns, so every load is coalesced)
+// and sums the pupil-masked differences and the pupil count down the
+// subaperture row.  The per-subaperture sums then add those column sums in
+// column order (a fixed order, so results are bit-reproducible).
+__global__ __launch_bounds__(SBLOCK) void slopes_kernel(const float* __restrict__ phase,
+                                                        const int32_t* __restrict__ valid,
+                                                        const uint8_t* __restrict__ pupil,
+                                                        int n_sub_x, int n_sub_y, int p, int nv,
+                                                        int subs_per_block,
+                                                        float* __restrict__ slopes) {
+  __shared__ float s_gx[SBLOCK], s_gy[SBLOCK], s_n[SBLOCK];
+  const int t = threadIdx.x;
+  const int n_runs = (n_sub_x + subs_per_block - 1) / subs_per_block;
+  const int v = blockIdx.x / n_runs;
+  const int u0 = (blockIdx.x - v * n_runs) * subs_per_block;
   const int i = blockIdx.y;
-  if (kk >= nv) return;
   const int W = n_sub_x * p, H = n_sub_y * p;
   const int Wh = W + 2;
-  const int k = valid[kk];
-  const int u = k % n_sub_x, v = k / n_sub_x;
+  const int nu = min(subs_per_block, n_sub_x - u0);
+  const int x = u0 * p + t;
   const float* ph = phase + (size_t)i * (size_t)(H + 2) * (size_t)Wh;
-  float sx = 0.f, sy = 0.f, cnt = 0.f;
-  for (int e = lane; e < p * p; e += 64) {
-    const int dy = e / p, dx = e - dy * p;
-    const int x = u * p + dx, y = v * p + dy;
-    if (pupil[(size_t)y * W + x]) {
+  float gx = 0.f, gy = 0.f, cnt = 0.f;
+  if (t < nu * p) {
+    // loads are unconditional (the halo keeps them in bounds) so that the
+    // p rows' loads are all in flight together; the pupil selects the terms
+#pragma unroll 4
+    for (int dy = 0; dy < p; ++dy) {
+      const int y = v * p + dy;
+      const bool in = pupil[(size_t)y * W + x] != 0;
       const size_t c = (size_t)(y + 1) * Wh + (x + 1);
-      sx += 0.5f * (ph[c + 1] - ph[c - 1]);
-      sy += 0.5f * (ph[c + Wh] - ph[c - Wh]);
-      cnt += 1.f;
+      const float ex = 0.5f * (ph[c + 1] - ph[c - 1]);
+      const float ey = 0.5f * (ph[c + Wh] - ph[c - Wh]);
+      gx += in ? ex : 0.f;
+      gy += in ? ey : 0.f;
+      cnt += in ? 1.f : 0.f;
     }
   }
-  sx = wave_sum(sx);
-  sy = wave_sum(sy);
-  cnt = wave_sum(cnt);
-  if (lane == 0) {
-    float* out = slopes + (size_t)i * 2 * nv;
-    out[kk] = sx / cnt;
-    out[nv + kk] = sy / cnt;
+  s_gx[t] = gx;
+  s_gy[t] = gy;
+  s_n[t] = cnt;
+  __syncthreads();
+  if (t >= nu) return;
+  const int k = v * n_sub_x + u0 + t;
+  int lo = 0, hi = nv - 1, kk = -1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int vm = valid[mid];
+    if (vm == k) {
+      kk = mid;
+      break;
+    }
+    if (vm < k) lo = mid + 1; else hi = mid - 1;
   }
+  if (kk < 0) return;
+  float sx = 0.f, sy = 0.f, n = 0.f;
+  for (int c = t * p; c < t * p + p; ++c) {
+    sx += s_gx[c];
+    sy += s_gy[c];
+    n += s_n[c];
+  }
+  float* out = slopes + (size_t)i * 2 * nv;
+  out[kk] = n > 0.f ? sx / n : 0.f;
+  out[nv + kk] = n > 0.f ? sy / n : 0.f;
 }
 
 }  // namespace
@@ -60,10 +85,13 @@ extern "C" int synim_sa_slopes(const float* phase, int n, const synim_wfs* wfs, 
   int st = validate_wfs(wfs);
   if (st != SYNIM_OK) return st;
   if (n < 1 || n > 65535) return SYNIM_E_SHAPE;
-  const int bx = (wfs->n_valid + WAVES - 1) / WAVES;
-  hipLaunchKernelGGL(slopes_kernel, dim3(bx, n), dim3(64 * WAVES), 0, (hipStream_t)stream, phase,
-                     wfs->valid_idx, wfs->pupil, wfs->n_sub_x, wfs->n_sub_y, wfs->p,
-                     wfs->n_valid, slopes);
+  if (wfs->p > SBLOCK) return SYNIM_E_SHAPE;
+  const int spb = SBLOCK / wfs->p;
+  const long bx = (long)wfs->n_sub_y * ((wfs->n_sub_x + spb - 1) / spb);
+  if (bx > 0x7fffffffL) return SYNIM_E_SHAPE;
+  hipLaunchKernelGGL(slopes_kernel, dim3((unsigned)bx, n), dim3(SBLOCK), 0, (hipStream_t)stream,
+                     phase, wfs->valid_idx, wfs->pupil, wfs->n_sub_x, wfs->n_sub_y, wfs->p,
+                     wfs->n_valid, spb, slopes);
   SYNIM_HIP_TRY(hipGetLastError());
   return SYNIM_OK;
 }

@@ -8,6 +8,10 @@ namespace synim {
 namespace {
 
 constexpr int WX = 64, WY = 4;   // one wave covers 64 consecutive output columns
+// Workgroups per launch the IF loop is split for: enough to fill 256 CUs many
+// times over, while each workgroup still reuses its FP64 source coordinates
+// over tens of IFs (16k, 32k and 128k measured within 8% of each other).
+constexpr long kTargetBlocks = 131072;
 
 __global__ __launch_bounds__(WX* WY) void warp_kernel(const float* __restrict__ ifs, int n,
                                                       int H_in, int W_in, MapD m, int H_out,
@@ -50,14 +54,39 @@ __global__ __launch_bounds__(WX* WY) void warp_kernel(const float* __restrict__ 
   const size_t plane_out = (size_t)Hh * Wh;
   const int i_begin = blockIdx.z * if_per_block;
   const int i_end = min(n, i_begin + if_per_block);
-  for (int i = i_begin; i < i_end; ++i) {
+  const size_t o0 = (size_t)oy * Wh + ox;
+  // UNR IFs per pass: all 4*UNR taps are loaded before the first one is used,
+  // so a thread keeps that many gathers in flight instead of one IF's four.
+  constexpr int UNR = 8;
+  int i = i_begin;
+  for (; i + UNR <= i_end; i += UNR) {
+    float v[UNR][4];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const float* F = ifs + (size_t)(i + u) * plane_in;
+      v[u][0] = t00 ? F[r0] : 0.0f;
+      v[u][1] = t01 ? F[r0 + 1] : 0.0f;
+      v[u][2] = t10 ? F[r1] : 0.0f;
+      v[u][3] = t11 ? F[r1 + 1] : 0.0f;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      float acc = 0.0f;
+      if (t00) acc = __fmaf_rn(w00, v[u][0], acc);
+      if (t01) acc = __fmaf_rn(w01, v[u][1], acc);
+      if (t10) acc = __fmaf_rn(w10, v[u][2], acc);
+      if (t11) acc = __fmaf_rn(w11, v[u][3], acc);
+      out[(size_t)(i + u) * plane_out + o0] = acc;
+    }
+  }
+  for (; i < i_end; ++i) {
     const float* F = ifs + (size_t)i * plane_in;
     float acc = 0.0f;
     if (t00) acc = __fmaf_rn(w00, F[r0], acc);
     if (t01) acc = __fmaf_rn(w01, F[r0 + 1], acc);
     if (t10) acc = __fmaf_rn(w10, F[r1], acc);
     if (t11) acc = __fmaf_rn(w11, F[r1 + 1], acc);
-    out[(size_t)i * plane_out + (size_t)oy * Wh + ox] = acc;
+    out[(size_t)i * plane_out + o0] = acc;
   }
 }
 
@@ -75,7 +104,7 @@ extern "C" int synim_affine_warp(const float* ifs, int n, int H_in, int W_in,
   const int Wh = W_out + 2 * halo, Hh = H_out + 2 * halo;
   const int bx = (Wh + WX - 1) / WX, by = (Hh + WY - 1) / WY;
   const long xy = (long)bx * by;
-  int ipb = (int)std::max(1L, (long)n * xy / 4096);
+  int ipb = (int)std::max(1L, (long)n * xy / kTargetBlocks);
   ipb = std::min(ipb, n);
   const int bz = (n + ipb - 1) / ipb;
   if (bz > 65535) return SYNIM_E_SHAPE;
