@@ -16,83 +16,204 @@
 namespace synim {
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;   // GEMM tile: 256 threads, 4x4 outputs each
+// ------------------------------------------------------------ FP32 GEMM
+// C[m][n] = alpha sum_k X(k, m) Y(k, n) (+ beta C[m][n]) (+ bias[n]) (then
+// ReLU), X(k, m) = X[k sxk + m sxm], Y(k, n) = Y[k syk + n syn], C row-major.
+// On the matrix cores: one 256-thread workgroup per 64x64 tile of C, each wave
+// a 32x32 quarter as 2x2 blocks of v_mfma_f32_16x16x4f32 (lane l feeds
+// A[l%16][l/16] and B[l/16][l%16] and holds D[4(l/16) + r][l%16], r = 0..3,
+// checked on the device).  K advances in chunks of 32 through two LDS buffers,
+// the next chunk's global loads in flight while the current one is multiplied.
+// Split K: workgroup z of a split launch sums k in [z kc, (z+1) kc) and writes
+// its partial tile to part[z][M][N]; gemm_reduce_kernel adds the partials in z
+// order (a fixed order: the result does not depend on scheduling) and applies
+// alpha, beta, bias and ReLU.
+constexpr int MT = 64, MK = 32, MPAD = 1;
+constexpr int MLOADS = MT * MK / 256;   // elements of one operand chunk per thread
 
-// C[M][N] = alpha * op(A) op(B) + beta * C (+ bias[n]) (then ReLU if relu).
-// op(A) is M x K (A stored [M][lda] or, transposed, [K][lda]); op(B) is K x N
-// (B stored [K][ldb] or, transposed, [N][ldb]).  FP32 FMA on 64x64 tiles
-// staged through LDS, 4x4 outputs per thread.
-template <bool TA, bool TB>
-__global__ __launch_bounds__(256) void gemm_kernel(int M, int N, int K, float alpha,
-                                                   const float* __restrict__ A, int lda,
-                                                   const float* __restrict__ B, int ldb,
-                                                   float beta, float* __restrict__ C, int ldc,
-                                                   const float* __restrict__ bias, int relu) {
-  __shared__ float As[BK][BM + 4];
-  __shared__ float Bs[BK][BN + 4];
-  const int tid = threadIdx.x;
-  const int tm = tid / 16, tn = tid % 16;   // 16 x 16 threads, 4 x 4 outputs each
-  const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
-  float acc[4][4] = {};
-  for (int k0 = 0; k0 < K; k0 += BK) {
-    // A tile: BM x BK elements, 4 per thread
-    for (int e = tid; e < BM * BK; e += 256) {
-      int mm, kk;
-      if (TA) { kk = e / BM; mm = e % BM; } else { mm = e / BK; kk = e % BK; }
-      const int gm = m0 + mm, gk = k0 + kk;
-      float v = 0.f;
-      if (gm < M && gk < K) v = TA ? A[(size_t)gk * lda + gm] : A[(size_t)gm * lda + gk];
-      As[kk][mm] = v;
-    }
-    for (int e = tid; e < BN * BK; e += 256) {
-      int nn, kk;
-      if (TB) { nn = e / BK; kk = e % BK; } else { kk = e / BN; nn = e % BN; }
-      const int gn = n0 + nn, gk = k0 + kk;
-      float v = 0.f;
-      if (gn < N && gk < K) v = TB ? B[(size_t)gn * ldb + gk] : B[(size_t)gk * ldb + gn];
-      Bs[kk][nn] = v;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < BK; ++kk) {
-      float a[4], b[4];
-#pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[kk][tm * 4 + i];
-#pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[kk][tn * 4 + j];
-#pragma unroll
-      for (int i = 0; i < 4; ++i)
-#pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = __fmaf_rn(a[i], b[j], acc[i][j]);
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gm = m0 + tm * 4 + i;
-    if (gm >= M) continue;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gn = n0 + tn * 4 + j;
-      if (gn >= N) continue;
-      float v = alpha * acc[i][j];
-      if (beta != 0.f) v += beta * C[(size_t)gm * ldc + gn];
-      if (bias) v += bias[gn];
-      if (relu) v = fmaxf(v, 0.f);
-      C[(size_t)gm * ldc + gn] = v;
-    }
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+struct MGemm {
+  int M, N, K;
+  const float* X;
+  long sxk, sxm;
+  const float* Y;
+  long syk, syn;
+  float* C;
+  long ldc;
+  float alpha, beta;
+  const float* bias;
+  int relu;
+  float* part;   // split launches: [splits][M][N]
+  int kc;        // K per split (a multiple of MK)
+  int splits;
+};
+
+// (kk, mm) of element q of this thread in an MK x MT chunk, consecutive
+// threads along the operand's unit stride
+__device__ __forceinline__ void mg_elem(long sk, int tid, int q, int& kk, int& mm) {
+  const int e = tid + 256 * q;
+  if (sk == 1) {
+    kk = e % MK;
+    mm = e / MK;
+  } else {
+    kk = e / MT;
+    mm = e % MT;
   }
 }
 
+__device__ __forceinline__ void mg_fetch(const float* P, long sk, long sm, int k0, int k1, int m0,
+                                         int M, int tid, float (&r)[MLOADS]) {
+#pragma unroll
+  for (int q = 0; q < MLOADS; ++q) {
+    int kk, mm;
+    mg_elem(sk, tid, q, kk, mm);
+    const int k = k0 + kk, m = m0 + mm;
+    r[q] = (k < k1 && m < M) ? P[(long)k * sk + (long)m * sm] : 0.f;
+  }
+}
+
+__device__ __forceinline__ void mg_put(long sk, int tid, const float (&r)[MLOADS],
+                                       float (*S)[MT + MPAD]) {
+#pragma unroll
+  for (int q = 0; q < MLOADS; ++q) {
+    int kk, mm;
+    mg_elem(sk, tid, q, kk, mm);
+    S[kk][mm] = r[q];
+  }
+}
+
+__device__ __forceinline__ float mg_epilogue(const MGemm& g, float acc, int m, int n) {
+  float v = g.alpha * acc;
+  if (g.beta != 0.f) v += g.beta * g.C[(long)m * g.ldc + n];
+  if (g.bias) v += g.bias[n];
+  if (g.relu) v = fmaxf(v, 0.f);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void gemm_mfma_kernel(MGemm g) {
+  const int m0 = blockIdx.y * MT, n0 = blockIdx.x * MT;
+  const int kb = blockIdx.z * g.kc, ke = min(g.K, kb + g.kc);
+  __shared__ float Xs[2][MK][MT + MPAD], Ys[2][MK][MT + MPAD];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  f32x4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+  float rx[MLOADS], ry[MLOADS];
+  mg_fetch(g.X, g.sxk, g.sxm, kb, ke, m0, g.M, tid, rx);
+  mg_fetch(g.Y, g.syk, g.syn, kb, ke, n0, g.N, tid, ry);
+  mg_put(g.sxk, tid, rx, Xs[0]);
+  mg_put(g.syk, tid, ry, Ys[0]);
+  __syncthreads();
+  const int nk = ke > kb ? (ke - kb + MK - 1) / MK : 0;
+  for (int c = 0; c < nk; ++c) {
+    const int buf = c & 1;
+    const bool more = c + 1 < nk;
+    if (more) {
+      mg_fetch(g.X, g.sxk, g.sxm, kb + (c + 1) * MK, ke, m0, g.M, tid, rx);
+      mg_fetch(g.Y, g.syk, g.syn, kb + (c + 1) * MK, ke, n0, g.N, tid, ry);
+    }
+#pragma unroll
+    for (int s = 0; s < MK / 4; ++s) {
+      const int kr = 4 * s + (lane >> 4);
+      float a[2], b[2];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) a[i] = Xs[buf][kr][wm + 16 * i + (lane & 15)];
+#pragma unroll
+      for (int j = 0; j < 2; ++j) b[j] = Ys[buf][kr][wn + 16 * j + (lane & 15)];
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      // the other buffer was last read in iteration c - 1, before its closing barrier
+      mg_put(g.sxk, tid, rx, Xs[buf ^ 1]);
+      mg_put(g.syk, tid, ry, Ys[buf ^ 1]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int m = m0 + wm + 16 * i + 4 * (lane >> 4) + r;
+        const int n = n0 + wn + 16 * j + (lane & 15);
+        if (m >= g.M || n >= g.N) continue;
+        if (g.splits > 1)
+          g.part[((long)blockIdx.z * g.M + m) * g.N + n] = acc[i][j][r];
+        else
+          g.C[(long)m * g.ldc + n] = mg_epilogue(g, acc[i][j][r], m, n);
+      }
+}
+
+__global__ __launch_bounds__(256) void gemm_reduce_kernel(MGemm g) {
+  const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (long)g.M * g.N) return;
+  const int m = (int)(i / g.N), n = (int)(i - (long)m * g.N);
+  float s = 0.f;
+  for (int z = 0; z < g.splits; ++z) s += g.part[(long)z * g.M * g.N + i];
+  g.C[(long)m * g.ldc + n] = mg_epilogue(g, s, m, n);
+}
+
+// K splits of an M x N x K product: enough workgroups to cover the CUs when
+// the tile grid alone is small, each split at least 4 chunks of K.
+int gemm_splits(int M, int N, int K) {
+  const long tiles = (long)((M + MT - 1) / MT) * ((N + MT - 1) / MT);
+  long s = (256 + tiles - 1) / tiles;
+  s = std::min<long>(s, std::max(1, K / (4 * MK)));
+  return (int)std::max<long>(1, std::min<long>(s, 16));
+}
+
+long gemm_part_floats(int M, int N, int K) {
+  const int s = gemm_splits(M, N, K);
+  return s > 1 ? (long)s * M * N : 0;
+}
+
+// op(A) is M x K (A stored [M][lda] or, transposed, [K][lda]); op(B) is K x N
+// (B stored [K][ldb] or, transposed, [N][ldb]).  part: gemm_part_floats floats.
 template <bool TA, bool TB>
 int gemm(int M, int N, int K, float alpha, const float* A, int lda, const float* B, int ldb,
-         float beta, float* C, int ldc, const float* bias, int relu, hipStream_t st) {
+         float beta, float* C, int ldc, const float* bias, int relu, float* part,
+         hipStream_t st) {
   if (M <= 0 || N <= 0 || K <= 0) return SYNIM_OK;
-  dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM);
+  MGemm g{};
+  g.M = M;
+  g.N = N;
+  g.K = K;
+  g.X = A;
+  g.sxk = TA ? lda : 1;
+  g.sxm = TA ? 1 : lda;
+  g.Y = B;
+  g.syk = TB ? 1 : ldb;
+  g.syn = TB ? ldb : 1;
+  g.C = C;
+  g.ldc = ldc;
+  g.alpha = alpha;
+  g.beta = beta;
+  g.bias = bias;
+  g.relu = relu;
+  g.splits = gemm_splits(M, N, K);
+  g.kc = (K + g.splits - 1) / g.splits;
+  g.kc = (g.kc + MK - 1) / MK * MK;
+  g.splits = (K + g.kc - 1) / g.kc;
+  g.part = part;
+  if (g.splits > 1 && !part) return SYNIM_E_WORKSPACE;
+  dim3 grid((N + MT - 1) / MT, (M + MT - 1) / MT, g.splits);
   if (grid.y > 65535) return SYNIM_E_SHAPE;
-  hipLaunchKernelGGL((gemm_kernel<TA, TB>), grid, dim3(256), 0, st, M, N, K, alpha, A, lda, B,
-                     ldb, beta, C, ldc, bias, relu);
+  hipLaunchKernelGGL(gemm_mfma_kernel, grid, dim3(256), 0, st, g);
   SYNIM_HIP_TRY(hipGetLastError());
+  if (g.splits > 1) {
+    const long n = (long)M * N;
+    hipLaunchKernelGGL(gemm_reduce_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, g);
+    SYNIM_HIP_TRY(hipGetLastError());
+  }
   return SYNIM_OK;
 }
 
@@ -232,12 +353,23 @@ int check_net(const synim_mlp* net) {
 }
 
 // Caller's scratch (floats): h1 [B][h1], h2 [B][h2] kept from the forward pass
-// for the backward pass, then dy [B][n_out], dh2 [B][h2], dh1 [B][h1], and the
-// used W1 columns (forward) or their gradient (backward) [h1][K].
+// for the backward pass, then dy [B][n_out], dh2 [B][h2], dh1 [B][h1], the
+// used W1 columns (forward) or their gradient (backward) [h1][K], and the
+// split-K partial products of the largest product of either pass.
 struct Scratch {
-  float *h1, *h2, *dy, *dh2, *dh1, *w1c;
+  float *h1, *h2, *dy, *dh2, *dh1, *w1c, *part;
   size_t total;
 };
+
+long part_floats(const synim_mlp& net, int B) {
+  const int K = net.len0 + net.len1;
+  const int shapes[8][3] = {{B, net.h1, K},         {B, net.h2, net.h1},    {B, net.n_out, net.h2},
+                            {net.n_out, net.h2, B}, {B, net.h2, net.n_out}, {net.h2, net.h1, B},
+                            {B, net.h1, net.h2},    {net.h1, K, B}};
+  long m = 0;
+  for (const auto& sh : shapes) m = std::max(m, gemm_part_floats(sh[0], sh[1], sh[2]));
+  return m;
+}
 
 Scratch scratch_layout(const synim_mlp& net, int B, float* base) {
   const size_t K = (size_t)net.len0 + net.len1;
@@ -254,6 +386,7 @@ Scratch scratch_layout(const synim_mlp& net, int B, float* base) {
   S.dh2 = take((size_t)B * net.h2);
   S.dh1 = take((size_t)B * net.h1);
   S.w1c = take((size_t)net.h1 * K);
+  S.part = take((size_t)part_floats(net, B));
   S.total = off;
   return S;
 }
@@ -313,13 +446,13 @@ extern "C" int synim_mlp_forward(const synim_mlp* net, const float* params, cons
   hipLaunchKernelGGL(gather_cols_kernel, dim3((unsigned)((nk + 255) / 256)), dim3(256), 0, st,
                      P + L.w1, net->h1, K, net->seg0, net->len0, net->seg1, net->n_in, w1c);
   SYNIM_HIP_TRY(hipGetLastError());
-  rc = gemm<false, true>(B, net->h1, K, 1.f, x, K, w1c, K, 0.f, h1, net->h1, P + L.b1, 1, st);
+  rc = gemm<false, true>(B, net->h1, K, 1.f, x, K, w1c, K, 0.f, h1, net->h1, P + L.b1, 1, S.part, st);
   if (rc != SYNIM_OK) return rc;
   rc = gemm<false, true>(B, net->h2, net->h1, 1.f, h1, net->h1, P + L.w2, net->h1, 0.f, h2,
-                         net->h2, P + L.b2, 1, st);
+                         net->h2, P + L.b2, 1, S.part, st);
   if (rc != SYNIM_OK) return rc;
   return gemm<false, true>(B, net->n_out, net->h2, 1.f, h2, net->h2, P + L.w3, net->h2, 0.f, y,
-                           net->n_out, P + L.b3, 0, st);
+                           net->n_out, P + L.b3, 0, S.part, st);
 }
 
 // Backward pass of the MSE loss after synim_mlp_forward on the same x and
@@ -349,13 +482,13 @@ extern "C" int synim_mlp_backward(const synim_mlp* net, const float* params, con
   SYNIM_HIP_TRY(hipGetLastError());
   // layer 3: dW3 = dy^T h2, db3 = sum dy, dh2 = dy W3 (masked by h2 > 0)
   rc = gemm<true, false>(net->n_out, net->h2, B, 1.f, dy, net->n_out, h2, net->h2, 0.f, G + L.w3,
-                         net->h2, nullptr, 0, st);
+                         net->h2, nullptr, 0, S.part, st);
   if (rc != SYNIM_OK) return rc;
   hipLaunchKernelGGL(colsum_kernel, dim3((net->n_out + 255) / 256), dim3(256), 0, st, dy, B,
                      net->n_out, G + L.b3);
   SYNIM_HIP_TRY(hipGetLastError());
   rc = gemm<false, false>(B, net->h2, net->n_out, 1.f, dy, net->n_out, P + L.w3, net->h2, 0.f,
-                          dh2, net->h2, nullptr, 0, st);
+                          dh2, net->h2, nullptr, 0, S.part, st);
   if (rc != SYNIM_OK) return rc;
   const long n2 = (long)B * net->h2;
   hipLaunchKernelGGL(relu_mask_kernel, dim3((unsigned)((n2 + 255) / 256)), dim3(256), 0, st, dh2,
@@ -363,20 +496,20 @@ extern "C" int synim_mlp_backward(const synim_mlp* net, const float* params, con
   SYNIM_HIP_TRY(hipGetLastError());
   // layer 2
   rc = gemm<true, false>(net->h2, net->h1, B, 1.f, dh2, net->h2, h1, net->h1, 0.f, G + L.w2,
-                         net->h1, nullptr, 0, st);
+                         net->h1, nullptr, 0, S.part, st);
   if (rc != SYNIM_OK) return rc;
   hipLaunchKernelGGL(colsum_kernel, dim3((net->h2 + 255) / 256), dim3(256), 0, st, dh2, B,
                      net->h2, G + L.b2);
   SYNIM_HIP_TRY(hipGetLastError());
   rc = gemm<false, false>(B, net->h1, net->h2, 1.f, dh2, net->h2, P + L.w2, net->h1, 0.f, dh1,
-                          net->h1, nullptr, 0, st);
+                          net->h1, nullptr, 0, S.part, st);
   if (rc != SYNIM_OK) return rc;
   const long n1 = (long)B * net->h1;
   hipLaunchKernelGGL(relu_mask_kernel, dim3((unsigned)((n1 + 255) / 256)), dim3(256), 0, st, dh1,
                      h1, n1);
   SYNIM_HIP_TRY(hipGetLastError());
   // layer 1: only the used columns of W1 get gradient, the rest is zero
-  rc = gemm<true, false>(net->h1, K, B, 1.f, dh1, net->h1, x, K, 0.f, dw1c, K, nullptr, 0, st);
+  rc = gemm<true, false>(net->h1, K, B, 1.f, dh1, net->h1, x, K, 0.f, dw1c, K, nullptr, 0, S.part, st);
   if (rc != SYNIM_OK) return rc;
   const long nw1 = (long)net->h1 * net->n_in;
   hipLaunchKernelGGL(fill_zero_kernel, dim3((unsigned)((nw1 + 255) / 256)), dim3(256), 0, st,

@@ -2,8 +2,8 @@
 
 * MLP kernels (forward, MSE backward, Adam) against the oracle's FP64 net on
   the same parameters and inputs, through both forward code paths (small
-  batches and tiled GEMMs with ragged tiles): outputs and gradients within
-  1e-4 of their maxima, Adam within 1e-6;
+  batches, and matrix-core GEMMs with ragged tiles and split-K products):
+  outputs and gradients within 1e-4 of their maxima, Adam within 1e-6;
 * probe slopes and their Jacobian from the batched 5-plane build against the
   oracle's IM and Jacobian of the probe maps (1e-5 / 1e-4 of the maxima);
 * Gauss-Newton on the device: noise-free probe slopes (oracle, FP64) give back
@@ -92,7 +92,7 @@ def test_mlp_forward_backward_parity(gpu_lib, B):
     assert np.all(W1[:, mask] == 0)
 
 
-@pytest.mark.parametrize("B", [1, 256])
+@pytest.mark.parametrize("B", [1, 37, 256, 1000])
 def test_mlp_parity_estimator_shape(gpu_lib, B):
     """The estimator's own network, 2 x 4000 -> 512 -> 256 -> 4, fed the compact
     inputs of the learned-fit workload (20 probes x 52 subapertures per channel,
@@ -134,6 +134,51 @@ def test_mlp_parity_estimator_shape(gpu_lib, B):
     for (lo, hi), ref in zip(lay, [a for pair in gref for a in pair]):
         got = g[lo:hi].reshape(ref.shape)
         assert rel_err(got, ref) <= 1e-4, (lo, hi, rel_err(got, ref))
+
+
+@pytest.mark.parametrize("B", [100, 333])
+def test_mlp_parity_split_products(gpu_lib, B):
+    """Layer widths and input lengths that are no multiples of the 64 x 64 GEMM
+    tiles or the 32-wide K chunks, so that the products split K into ragged
+    parts (the last one shorter) whose partial sums are reduced afterwards."""
+    import torch
+    from paper_2606_07759_amd import learned
+    S = gpu_lib
+    say(f"[case] mlp split products B={B}")
+    segs = ((100, 350), (900, 351))
+    net = S.Mlp(1500, 200, 70, 3, segs)
+    packed = learned.he_init(net, 5)
+    rng = np.random.default_rng(300 + B)
+    for (lo, hi), is_bias in zip(net.layout(), (False, True) * 3):
+        if is_bias:
+            packed[lo:hi] = (0.05 * rng.standard_normal(hi - lo)).astype(np.float32)
+    xc = rng.standard_normal((B, 701)).astype(np.float32)
+    t = rng.uniform(-1, 1, (B, 3)).astype(np.float32)
+    dev = torch.device("cuda:0")
+    params = torch.from_numpy(packed).to(dev)
+    scratch = net.scratch(B, device=dev)
+    xd = torch.from_numpy(xc).to(dev)
+    y = net.forward(params, xd, scratch)
+    grads = torch.empty_like(params)
+    net.backward(params, xd, scratch, y, torch.from_numpy(t).to(dev), grads)
+    torch.cuda.synchronize()
+    lay = net.layout()
+    shapes = [(200, 1500), (200,), (70, 200), (70,), (3, 70), (3,)]
+    P = [packed[lo:hi].astype(np.float64).reshape(sh) for (lo, hi), sh in zip(lay, shapes)]
+    oparams = [(P[0], P[1]), (P[2], P[3]), (P[4], P[5])]
+    x = np.zeros((B, 1500))
+    x[:, 100:450] = xc[:, :350]
+    x[:, 900:1251] = xc[:, 350:]
+    yref, acts = omlp.forward(x, oparams)
+    assert rel_err(y.cpu().numpy(), yref) <= 1e-4
+    gref = omlp.backward(acts, oparams, t.astype(np.float64))
+    g = grads.cpu().numpy()
+    for (lo, hi), ref in zip(lay, [a for pair in gref for a in pair]):
+        got = g[lo:hi].reshape(ref.shape)
+        assert rel_err(got, ref) <= 1e-4, (lo, hi, rel_err(got, ref))
+    # a second forward pass through the same scratch is bitwise the same
+    y2 = net.forward(params, xd, scratch)
+    assert torch.equal(y, y2)
 
 
 def test_adam_step_parity(gpu_lib):
