@@ -472,10 +472,14 @@ __device__ int find_valid(const int32_t* __restrict__ valid, int nv, int k) {
 // holding a weight), or hr.x >= hr.y for an empty slot.  Writes rows[t*BHmax
 // + r], tile_info[t]; flags bit 1 of status[0] for a tile that does not fit,
 // counts non-empty tiles in status[1].  256 threads.
+// pad_odd: every non-empty row is widened to 4 mod 8 floats, so that rows
+// packed one after the other start 4 * (odd) floats apart and the lanes that
+// read the same column of eight consecutive rows hit eight different LDS banks
+// (with widths a multiple of 32 floats they would all hit one).
 template <class SlotOf>
 __device__ __forceinline__ void build_tile_rows(int t, int NS, int PW, int BHmax, int cap_floats,
                                                 SlotOf slot_of, int2* rows_out, int4* tile_info,
-                                                int* status) {
+                                                int* status, bool pad_odd = false) {
   __shared__ int s_ox[1024], s_oy[1024], s_oe[1024];
   __shared__ int s_x0[MAX_TILE_ROWS], s_w[MAX_TILE_ROWS];
   __shared__ int s_lo[MAX_TILE_ROWS], s_hi[MAX_TILE_ROWS];
@@ -537,8 +541,9 @@ __device__ __forceinline__ void build_tile_rows(int t, int NS, int PW, int BHmax
       s_w[r] = 0;
     } else {
       const int x0 = floor_div(lo, 4) * 4;
+      const int w = (hi - x0 + 3) / 4 * 4;
       s_x0[r] = x0;
-      s_w[r] = (hi - x0 + 3) / 4 * 4;
+      s_w[r] = pad_odd && (w & 4) == 0 ? w + 4 : w;
     }
   }
   __syncthreads();
@@ -621,7 +626,7 @@ __global__ __launch_bounds__(256) void plan_rows_shared_kernel(
           hr = J.hrows[e & 0xFFFFF];
         }
       },
-      rows_out, tile_info, status);
+      rows_out, tile_info, status, true);
 }
 
 __global__ void zero_ints_kernel(int* __restrict__ p, int n) {
@@ -1637,12 +1642,17 @@ void host_origin(const MapD& m, int u, int v, int p, int* ox, int* oy) {
 // rounding (one pixel) plus one pixel of map drift before set_maps re-bins.
 constexpr int SHARED_MARGIN = 2;
 
-// Bins the subapertures of every pair of each DM group into shared tiles for
-// variant v: cells of cell_x x cell_y pixels over the IF grid by patch
-// origin, a cell with more than NSLOT subapertures split into NSLOT-sized
-// runs in (y, x) order.  The cell size minimises the staged 128-byte lines
-// (rows x line span per tile) among the sizes whose tiles provably fit the
-// stage buffers.
+// Packs the subapertures of every pair of each DM group into shared tiles for
+// variant v.  The slots of a group are ordered by the IF-space cell (cell_x x
+// cell_y pixels) their patch origin falls in, then by origin, and taken in that
+// order into tiles as long as a tile holds at most NSLOT subapertures and its
+// staged box (origin spread + patch + the drift margin on every side, rows
+// padded to 4 mod 8 floats) provably fits the stage buffers.  Tiles therefore
+// come out nearly full: every lane of a tile runs the contraction whether its
+// slot holds a subaperture or not, and the batch is bound by that arithmetic.
+// The cell size is the one that minimises an estimate of the batch time: lane
+// FMAs of all tiles plus the staged 128-byte lines at about 228 lane FMAs each
+// (the ratio of the batch's FMA rate to its DMA streaming rate).
 int build_shared(synim_batch* b, const Variant& v) {
   const int NS = v.BLOCK / v.LPS, PH = v.PH(), PW = v.PW, cap = v.cap_floats();
   const int np = (int)b->pairs.size();
@@ -1666,20 +1676,72 @@ int build_shared(synim_batch* b, const Variant& v) {
     }
   }
   if (np >= (1 << 11)) return SYNIM_E_UNSUPPORTED;   // pair index field of a slot
+  // staged-box bound of a tile whose origins span [x0, x1] x [y0, y1]
+  auto box = [&](int x0, int x1, int y0, int y1, int* bw, int* bh) {
+    *bw = (x1 - x0 + PW + 2 * SHARED_MARGIN + 3 + 3) / 4 * 4 + 4;   // + 4: row padding
+    *bh = y1 - y0 + PH + 2 * SHARED_MARGIN;
+  };
+  {
+    int bw, bh;
+    box(0, 0, 0, 0, &bw, &bh);
+    if ((long)bw * bh > cap || bh > MAX_TILE_ROWS) return SYNIM_E_UNSUPPORTED;
+  }
+  auto order_by_cells = [&](std::vector<Sl>& sl, int cx, int cy) {
+    std::stable_sort(sl.begin(), sl.end(), [&](const Sl& x, const Sl& y) {
+      const int cxa = floor_div(x.ox, cx), cya = floor_div(x.oy, cy);
+      const int cxb = floor_div(y.ox, cx), cyb = floor_div(y.oy, cy);
+      if (cya != cyb) return cya < cyb;
+      if (cxa != cxb) return cxa < cxb;
+      if (x.oy != y.oy) return x.oy < y.oy;
+      return x.ox < y.ox;
+    });
+  };
+  // greedy packing of ordered slots; emit(begin, end, box width, box rows)
+  auto pack = [&](const std::vector<Sl>& sl, auto&& emit) {
+    size_t t0 = 0;
+    int x0 = 0, x1 = 0, y0 = 0, y1 = 0;
+    for (size_t i = 0; i < sl.size(); ++i) {
+      if (i == t0) {
+        x0 = x1 = sl[i].ox;
+        y0 = y1 = sl[i].oy;
+        continue;
+      }
+      const int nx0 = std::min(x0, sl[i].ox), nx1 = std::max(x1, sl[i].ox);
+      const int ny0 = std::min(y0, sl[i].oy), ny1 = std::max(y1, sl[i].oy);
+      int bw, bh;
+      box(nx0, nx1, ny0, ny1, &bw, &bh);
+      if (i - t0 >= (size_t)NS || (long)bw * bh > cap || bh > MAX_TILE_ROWS) {
+        box(x0, x1, y0, y1, &bw, &bh);
+        emit(t0, i, bw, bh);
+        t0 = i;
+        x0 = x1 = sl[i].ox;
+        y0 = y1 = sl[i].oy;
+      } else {
+        x0 = nx0;
+        x1 = nx1;
+        y0 = ny0;
+        y1 = ny1;
+      }
+    }
+    if (t0 < sl.size()) {
+      int bw, bh;
+      box(x0, x1, y0, y1, &bw, &bh);
+      emit(t0, sl.size(), bw, bh);
+    }
+  };
   static const int kCells[] = {8, 12, 16, 20, 24, 32, 40, 48, 64, 96, 128};
+  constexpr double kLineFmas = 228.0;
+  const double fmas_per_tile = (double)NS * PH * PW * 2;
   double best = 1e300;
   int bx = 0, by = 0;
   for (int cx : kCells)
     for (int cy : kCells) {
-      const int BW = (cx + PW + 2 * SHARED_MARGIN + 3 + 3) / 4 * 4;
-      const int BH = cy + PH + 2 * SHARED_MARGIN;
-      if ((long)BW * BH > cap || BH > MAX_TILE_ROWS) continue;
       double cost = 0;
-      for (const auto& sl : per_group) {
-        std::map<std::pair<int, int>, int> cnt;
-        for (const Sl& e : sl) ++cnt[{floor_div(e.oy, cy), floor_div(e.ox, cx)}];
-        for (const auto& kv : cnt)
-          cost += (double)((kv.second + NS - 1) / NS) * BH * (BW / 32.0 + 1.0);
+      for (auto sl : per_group) {
+        order_by_cells(sl, cx, cy);
+        pack(sl, [&](size_t, size_t, int bw, int bh) {
+          cost += fmas_per_tile + kLineFmas * bh * (bw / 32.0 + 1.0);
+        });
       }
       if (cost < best) {
         best = cost;
@@ -1691,44 +1753,35 @@ int build_shared(synim_batch* b, const Variant& v) {
   b->cell_x = bx;
   b->cell_y = by;
   b->jNS = NS;
-  b->jBHmax = by + PH + 2 * SHARED_MARGIN;
   b->jslots_host.clear();
   b->jorigin_host.clear();
   b->jgroups_host.assign(b->n_groups, make_int2(0, 0));
-  int n_jt = 0;
+  int n_jt = 0, bh_max = 0;
   for (int gi = 0; gi < b->n_groups; ++gi) {
     std::vector<Sl> sl = per_group[gi];
-    std::stable_sort(sl.begin(), sl.end(), [&](const Sl& x, const Sl& y) {
-      const int cxa = floor_div(x.ox, bx), cya = floor_div(x.oy, by);
-      const int cxb = floor_div(y.ox, bx), cyb = floor_div(y.oy, by);
-      if (cya != cyb) return cya < cyb;
-      if (cxa != cxb) return cxa < cxb;
-      if (x.oy != y.oy) return x.oy < y.oy;
-      return x.ox < y.ox;
-    });
+    order_by_cells(sl, bx, by);
     b->jgroups_host[gi] = make_int2(n_jt, 0);
-    size_t i = 0;
-    while (i < sl.size()) {
-      const int cx = floor_div(sl[i].ox, bx), cy = floor_div(sl[i].oy, by);
-      size_t j = i;
-      while (j < sl.size() && floor_div(sl[j].ox, bx) == cx && floor_div(sl[j].oy, by) == cy) ++j;
-      for (size_t t0 = i; t0 < j; t0 += NS) {
-        for (int s = 0; s < NS; ++s) {
-          const size_t at = t0 + s;
-          if (at < j) {
-            b->jslots_host.push_back((sl[at].pair << 20) | sl[at].kk);
-            b->jorigin_host.push_back(make_int2(sl[at].ox, sl[at].oy));
-          } else {
-            b->jslots_host.push_back(-1);
-            b->jorigin_host.push_back(make_int2(INT_MIN, INT_MIN));
-          }
+    pack(sl, [&](size_t t0, size_t t1, int, int bh) {
+      for (int s = 0; s < NS; ++s) {
+        const size_t at = t0 + s;
+        if (at < t1) {
+          b->jslots_host.push_back((sl[at].pair << 20) | sl[at].kk);
+          b->jorigin_host.push_back(make_int2(sl[at].ox, sl[at].oy));
+        } else {
+          b->jslots_host.push_back(-1);
+          b->jorigin_host.push_back(make_int2(INT_MIN, INT_MIN));
         }
-        ++n_jt;
-        ++b->jgroups_host[gi].y;
       }
-      i = j;
-    }
+      bh_max = std::max(bh_max, bh);
+      ++n_jt;
+      ++b->jgroups_host[gi].y;
+    });
   }
+  // row tables sized for the most rows any tile can have (its narrowest box
+  // at the stage capacity), so that re-packing for new maps keeps the layout
+  int bw_min, bh_one;
+  box(0, 0, 0, 0, &bw_min, &bh_one);
+  b->jBHmax = std::max(bh_max, std::min(MAX_TILE_ROWS, cap / bw_min));
   b->n_jt = n_jt;
   return SYNIM_OK;
 }

@@ -163,9 +163,12 @@ __device__ __forceinline__ float4* stage_buf() {
   return b;
 }
 
-// s_waitcnt vmcnt(n) for a uniform runtime n in [0, 63] (the immediate must be
-// a constant: a jump table over every value).
+// s_waitcnt vmcnt(n) for a wave-uniform runtime n in [0, 63] (the immediate
+// must be a constant: a branch over every value).  n is moved to a scalar
+// register first: where the compiler cannot prove it uniform it would branch
+// on a vector compare per value, with exec-mask bookkeeping at every level.
 __device__ __forceinline__ void wait_vm(int n) {
+  n = __builtin_amdgcn_readfirstlane(n);
   switch (n) {
 #define SYNIM_W(k) case k: __builtin_amdgcn_s_waitcnt(waitcnt_vm(k)); break;
 #define SYNIM_W8(k) SYNIM_W(k) SYNIM_W(k + 1) SYNIM_W(k + 2) SYNIM_W(k + 3) SYNIM_W(k + 4) \
