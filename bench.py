@@ -29,8 +29,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "IM columns/s & % HBM roofline; misreg-fit ms, learned vs Gauss-Newton"
 PEAK_HBM_GBS = 8000.0
-STREAM_SRC = os.path.join(ROOT, "paper_2606_07759_amd", "csrc", "stream.hpp")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "im_stream_elt_traffic.json")
+MCAO_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "im_stream_mcao_traffic.json")
 
 
 def log(*a):
@@ -138,15 +138,19 @@ def cpu_baseline(seed: int, target_s: float):
             "workers_note": "worker processes capped at 16, one GPU's share of the host CPUs"}
 
 
-def stored_traffic(n_launch_bytes):
-    """HBM traffic of the streaming kernel from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+def stored_traffic(record=TRAFFIC_FILE):
+    """HBM bytes per launch of a streaming kernel (rocprofv3 FETCH_SIZE and
+    WRITE_SIZE, scaled by a plain copy's counts) from a committed counter
+    record, if it was taken on the current source of the files it names (the
+    stream kernel and the plan that builds its tiles); else None."""
     try:
-        with open(TRAFFIC_FILE) as f:
+        with open(record) as f:
             rec = json.load(f)
-        with open(STREAM_SRC, "rb") as f:
-            h = hashlib.sha256(f.read()).hexdigest()[:16]
-        if rec.get("kernel_sha") != h:
+        h = hashlib.sha256()
+        for src in rec["sources"]:
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if rec.get("kernel_sha") != h.hexdigest()[:16]:
             return None
         return float(rec["bytes_per_launch"])
     except (OSError, ValueError, KeyError):
@@ -207,6 +211,7 @@ def mcao_leg(synim, dev, reps: int = 10):
             "ms_per_batch": ms, "im_columns": cols, "columns_per_s": cols / (ms * 1e-3),
             "algorithmic_bytes": byts, "achieved_GBs": byts / (ms * 1e-3) / 1e9,
             "frac_of_hbm_peak": byts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+            "traffic": stored_traffic(MCAO_TRAFFIC_FILE),
             "config": cfg_b, "autotune_ms": tuned}
 
 
@@ -482,7 +487,7 @@ def main():
     ms_step = wall * 1e3 / args.steps
     apply_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     achieved = launch_bytes / (apply_ms * 1e-3) / 1e9
-    traffic = stored_traffic(launch_bytes)
+    traffic = stored_traffic(TRAFFIC_FILE)
     legs = {}
     if not args.no_legs:
         log("legs: standalone warp and slopes")
