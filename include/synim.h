@@ -334,18 +334,19 @@ int synim_plan_oob(const void* ws, int64_t* host_count, void* stream);
 /* ------------------------------------------------------- multi-pair batch
  * Every (WFS, DM) pair of a multi-WFS system (e.g. 6 LGS WFS x 3 DMs) built in
  * one persistent launch - the multi-WFS batch of Sec. 4.2, where each DM's IF
- * stack is fetched once for all the WFS that see it: for IM batches
- * (planes = 1) the subapertures of every WFS of a DM are binned by the cell
- * of the IF grid their weight patches start in, and one staging of a cell's
- * IF rows serves all of them (the tiles' staged boxes overlap by the patch
- * halo, so HBM reads a DM's stack about twice rather than once per WFS).  Pairs may have their own map (cone
- * effect, off-axis footprint), WFS (uneven valid-subaperture counts) and DM
- * (uneven actuator counts).  The maps live in device memory, so a graph
- * captured by synim_batch_run_graph replays after synim_batch_set_maps
- * without re-capture.  The kernel configuration is chosen at creation from
- * the initial maps; later maps must not need larger weight patches or tiles
- * (else synim_batch_status reports bits 0/1 and the affected slopes are
- * missing - create a new batch). */
+ * stack is fetched once for all the WFS that see it.  For IM batches
+ * (planes = 1) the subapertures of every WFS of a DM are packed, in the order
+ * of the IF-grid cells their weight patches start in, into full tiles whose
+ * staged box fits the stage buffers, and one staging of a tile's IF rows
+ * serves every WFS in it.  The tiles' staged boxes overlap by the patch halo,
+ * so HBM still reads a DM's stack more than once (about 2.4 times for the
+ * 6 x 3 MCAO system, against 7.7 times with one staging per pair).  Pairs may
+ * have their own map (cone effect, off-axis footprint), WFS (uneven
+ * valid-subaperture counts) and DM (uneven actuator counts).  The maps live in
+ * device memory, so a graph captured by synim_batch_run_graph replays after
+ * synim_batch_set_maps without re-capture.  The kernel configuration is chosen
+ * at creation from the initial maps; synim_batch_set_maps checks later maps
+ * against it. */
 
 typedef struct {
   const float* ifs;           /* device [n_act][H_in][W_in]                     */
