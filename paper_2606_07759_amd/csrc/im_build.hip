@@ -472,14 +472,16 @@ __device__ int find_valid(const int32_t* __restrict__ valid, int nv, int k) {
 // holding a weight), or hr.x >= hr.y for an empty slot.  Writes rows[t*BHmax
 // + r], tile_info[t]; flags bit 1 of status[0] for a tile that does not fit,
 // counts non-empty tiles in status[1].  256 threads.
-// pad_odd: every non-empty row is widened to 4 mod 8 floats, so that rows
-// packed one after the other start 4 * (odd) floats apart and the lanes that
-// read the same column of eight consecutive rows hit eight different LDS banks
-// (with widths a multiple of 32 floats they would all hit one).
+// pitched: the rows are staged at one pitch per tile instead of packed, the
+// widest row's width rounded to 4 mod 8 floats, so that the lanes reading one
+// column of eight consecutive rows hit eight different LDS banks (packed rows
+// of varying widths start at offsets that collide).  Then rows[t*BHmax + r] =
+// (first column, width of row r) and tile_info[t].w = the pitch; the vectors
+// past a row's width are not fetched (the DMA zero-fills them).
 template <class SlotOf>
 __device__ __forceinline__ void build_tile_rows(int t, int NS, int PW, int BHmax, int cap_floats,
                                                 SlotOf slot_of, int2* rows_out, int4* tile_info,
-                                                int* status, bool pad_odd = false) {
+                                                int* status, bool pitched = false) {
   __shared__ int s_ox[1024], s_oy[1024], s_oe[1024];
   __shared__ int s_x0[MAX_TILE_ROWS], s_w[MAX_TILE_ROWS];
   __shared__ int s_lo[MAX_TILE_ROWS], s_hi[MAX_TILE_ROWS];
@@ -541,12 +543,31 @@ __device__ __forceinline__ void build_tile_rows(int t, int NS, int PW, int BHmax
       s_w[r] = 0;
     } else {
       const int x0 = floor_div(lo, 4) * 4;
-      const int w = (hi - x0 + 3) / 4 * 4;
       s_x0[r] = x0;
-      s_w[r] = pad_odd && (w & 4) == 0 ? w + 4 : w;
+      s_w[r] = (hi - x0 + 3) / 4 * 4;
     }
   }
   __syncthreads();
+  if (pitched) {
+    __shared__ int s_pitch;
+    if (tid == 0) s_pitch = 0;
+    __syncthreads();
+    for (int r = tid; r < bh; r += blockDim.x) atomicMax(&s_pitch, s_w[r]);
+    __syncthreads();
+    const int pitch = (s_pitch & 4) == 0 ? s_pitch + 4 : s_pitch;   // 4 mod 8 floats
+    for (int r = tid; r < bh; r += blockDim.x)
+      rows_out[(size_t)t * BHmax + r] = make_int2(s_x0[r], s_w[r]);
+    if (tid == 0) {
+      if ((long)bh * pitch > cap_floats) {
+        atomicOr(status, 2);   // tile skipped: its slopes stay unwritten
+        tile_info[t] = make_int4(0, 0, 0, 0);
+      } else {
+        tile_info[t] = make_int4(y0, bh, bh * pitch, pitch);
+        atomicAdd(status + 1, 1);
+      }
+    }
+    return;
+  }
   // packed offsets: exclusive prefix sum of the row widths (Hillis-Steele in
   // LDS over blocks of blockDim rows, carried across blocks)
   __shared__ int s_scan[256];
@@ -1676,9 +1697,10 @@ int build_shared(synim_batch* b, const Variant& v) {
     }
   }
   if (np >= (1 << 11)) return SYNIM_E_UNSUPPORTED;   // pair index field of a slot
-  // staged-box bound of a tile whose origins span [x0, x1] x [y0, y1]
+  // staged-box bound of a tile whose origins span [x0, x1] x [y0, y1]: rows
+  // at one pitch, the widest row rounded to 4 mod 8 floats (+ 4)
   auto box = [&](int x0, int x1, int y0, int y1, int* bw, int* bh) {
-    *bw = (x1 - x0 + PW + 2 * SHARED_MARGIN + 3 + 3) / 4 * 4 + 4;   // + 4: row padding
+    *bw = (x1 - x0 + PW + 2 * SHARED_MARGIN + 3 + 3) / 4 * 4 + 4;
     *bh = y1 - y0 + PH + 2 * SHARED_MARGIN;
   };
   {

@@ -357,7 +357,9 @@ im_stream_kernel(StreamArgs g) {
     const size_t plane_in = (size_t)P.H_in * P.W_in;
     const int4 ti = shared ? g.jinfo[tile] : P.tile_info[tile];
     if (ti.y == 0) continue;   // empty tile
-    const int y0 = ti.x, nfl = ti.z;
+    // ti.w > 0: rows staged at that pitch, row table (first column, width);
+    // else packed, row table (first column, packed offset)
+    const int y0 = ti.x, nfl = ti.z, pitch = ti.w;
     // the tile's row table goes to LDS (one coalesced load), where the row
     // lookups below run without a memory round trip each
     {
@@ -403,7 +405,7 @@ im_stream_kernel(StreamArgs g) {
       base[i] = 0;
       if (kk >= 0 && pr >= hr.x && pr < hr.y) {
         const int2 rw = rows[o.y + pr - y0];
-        base[i] = rw.y + (o.x - rw.x);
+        base[i] = (pitch > 0 ? (o.y + pr - y0) * pitch : rw.y) + (o.x - rw.x);
       }
     }
 
@@ -427,15 +429,27 @@ im_stream_kernel(StreamArgs g) {
       const int kp = KPMAX == 1 ? (fo < nfl ? 0 : 1) : (nfl > 0 ? fo / nfl : KP);
       if (kp < KP) {
         const int fr = fo - kp * nfl;          // offset within that actuator's rows
-        int lo = 0, hi = ti.y - 1;             // last row whose offset is <= fr
-        while (lo < hi) {
-          const int mid = (lo + hi + 1) >> 1;
-          if (rows[mid].y <= fr) lo = mid; else hi = mid - 1;
+        int lo, c;
+        bool in_row = true;
+        if (pitch > 0) {
+          // rows at one pitch: vectors past a row's width are not fetched
+          lo = fr / pitch;
+          c = fr - lo * pitch;
+          in_row = lo < ti.y && c < rows[lo].y;
+        } else {
+          lo = 0;                              // last row whose offset is <= fr
+          int hi = ti.y - 1;
+          while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (rows[mid].y <= fr) lo = mid; else hi = mid - 1;
+          }
+          c = fr - rows[lo].y;
         }
-        const int2 rw = rows[lo];
-        const int gx = rw.x + (fr - rw.y), gy = y0 + lo;
-        if (gx >= 0 && gx + VW <= P.W_in && gy >= 0 && gy < P.H_in)
-          v = (unsigned)kp * (unsigned)plane_bytes + (unsigned)(gy * P.W_in + gx) * 4u;
+        if (in_row) {
+          const int gx = rows[lo].x + c, gy = y0 + lo;
+          if (gx >= 0 && gx + VW <= P.W_in && gy >= 0 && gy < P.H_in)
+            v = (unsigned)kp * (unsigned)plane_bytes + (unsigned)(gy * P.W_in + gx) * 4u;
+        }
       }
       voff[j] = v;
     }
