@@ -410,6 +410,9 @@ def main():
                          "(the workload of the fit's kernel trace)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy (calibrates HBM byte counters)")
+    ap.add_argument("--misreg-only", action="store_true",
+                    help="only run the learned-misregistration leg (sizes from --misreg-train, "
+                         "--misreg-eval, --misreg-epochs) and print its figures")
     ap.add_argument("--mcao-only", action="store_true",
                     help="only run the MCAO batch leg (the workload of its kernel trace) and "
                          "print its figures")
@@ -427,6 +430,10 @@ def main():
     if args.misreg_replay:
         from paper_2606_07759_amd import learned
         learned.replay_fits()
+        return
+    if args.misreg_only:
+        print(json.dumps(misreg_leg(args.misreg_train, args.misreg_eval, args.misreg_epochs)),
+              flush=True)
         return
     if args.mcao_only:
         import paper_2606_07759_amd as synim
