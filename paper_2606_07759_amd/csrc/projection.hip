@@ -74,14 +74,17 @@ __global__ __launch_bounds__(256) void proj_sample_kernel(SampleArgs g) {
 // ---------------------------------------------------------------- FP64 GEMM
 // C[m][n] = alpha sum_k X(k, m) Y(k, n) + beta C[m][n], X(k, m) = X[k sxk + m sxm],
 // Y(k, n) = Y[k syk + n syn], C row-major with ldc.  One workgroup of 256
-// threads per 128x128 tile of C; each wave owns a 64x64 quarter as 4x4 blocks
-// of v_mfma_f64_16x16x4f64 (lane l feeds A[l%16][l/16] and B[l/16][l%16]
-// and holds D[4r + l/16][l%16], r = 0..3).  K advances in chunks of 16 through
-// two LDS buffers: the next chunk's global loads are in flight while the
-// current one feeds the matrix cores.  lower: only tiles with some m >= n (a
-// symmetric result's lower triangle) are computed.
-constexpr int GT = 128, GK = 16, GPAD = 2;
-constexpr int GLOADS = GK * GT / 256;   // elements of one operand chunk per thread
+// threads per (32 BI) x (32 BJ) tile of C; each wave owns a (16 BI) x (16 BJ)
+// quarter as BI x BJ blocks of v_mfma_f64_16x16x4f64 (lane l feeds
+// A[l%16][l/16] and B[l/16][l%16] and holds D[4r + l/16][l%16], r = 0..3).  K
+// advances in chunks of 16 through two LDS buffers: the next chunk's global
+// loads are in flight while the current one feeds the matrix cores.  lower:
+// only tiles with some m >= n (a symmetric result's lower triangle) are
+// computed.  Two shapes: 128 x 128 (two workgroups per CU) for small products,
+// 256 x 128 (one per CU, each wave's 8 x 4 accumulator blocks in the
+// accumulation registers) for large ones, which halves the operand bytes each
+// flop needs from L2 along m.
+constexpr int GK = 16, GPAD = 2;
 
 struct GemmArgs {
   int M, N, K;
@@ -95,90 +98,97 @@ struct GemmArgs {
   int lower;
 };
 
-// (kk, mm) of element q of this thread in a 16 x 128 chunk, reading along the
+// (kk, mm) of element q of this thread in a GK x T chunk, reading along the
 // operand's unit stride
+template <int T>
 __device__ __forceinline__ void gemm_elem(long sk, int tid, int q, int& kk, int& mm) {
   const int e = tid + 256 * q;
   if (sk == 1) {
     kk = e % GK;
     mm = e / GK;
   } else {
-    kk = e / GT;
-    mm = e % GT;
+    kk = e / T;
+    mm = e % T;
   }
 }
 
+template <int T>
 __device__ __forceinline__ void gemm_fetch(const double* P, long sk, long sm, int k0, int m0,
-                                           int K, int M, int tid, double (&r)[GLOADS]) {
+                                           int K, int M, int tid, double (&r)[GK * T / 256]) {
 #pragma unroll
-  for (int q = 0; q < GLOADS; ++q) {
+  for (int q = 0; q < GK * T / 256; ++q) {
     int kk, mm;
-    gemm_elem(sk, tid, q, kk, mm);
+    gemm_elem<T>(sk, tid, q, kk, mm);
     const int k = k0 + kk, m = m0 + mm;
     r[q] = (k < K && m < M) ? P[(long)k * sk + (long)m * sm] : 0.0;
   }
 }
 
-__device__ __forceinline__ void gemm_put(long sk, int tid, const double (&r)[GLOADS],
-                                         double (*S)[GT + GPAD]) {
+template <int T>
+__device__ __forceinline__ void gemm_put(long sk, int tid, const double (&r)[GK * T / 256],
+                                         double (*S)[T + GPAD]) {
 #pragma unroll
-  for (int q = 0; q < GLOADS; ++q) {
+  for (int q = 0; q < GK * T / 256; ++q) {
     int kk, mm;
-    gemm_elem(sk, tid, q, kk, mm);
+    gemm_elem<T>(sk, tid, q, kk, mm);
     S[kk][mm] = r[q];
   }
 }
 
+template <int BI, int BJ>
 __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
-  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-  if (g.lower && m0 + GT - 1 < n0) return;   // tile wholly above the diagonal
-  __shared__ double Xs[2][GK][GT + GPAD], Ys[2][GK][GT + GPAD];
+  constexpr int TM = 32 * BI, TN = 32 * BJ;
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TN;
+  if (g.lower && m0 + TM - 1 < n0) return;   // tile wholly above the diagonal
+  __shared__ double Xs[2][GK][TM + GPAD], Ys[2][GK][TN + GPAD];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
-  d4 acc[4][4];
+  const int wm = (wave >> 1) * 16 * BI, wn = (wave & 1) * 16 * BJ;
+  d4 acc[BI][BJ];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-  double rx[GLOADS], ry[GLOADS];
-  gemm_fetch(g.X, g.sxk, g.sxm, 0, m0, g.K, g.M, tid, rx);
-  gemm_fetch(g.Y, g.syk, g.syn, 0, n0, g.K, g.N, tid, ry);
-  gemm_put(g.sxk, tid, rx, Xs[0]);
-  gemm_put(g.syk, tid, ry, Ys[0]);
+    for (int j = 0; j < BJ; ++j) acc[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+  double rx[GK * TM / 256], ry[GK * TN / 256];
+  gemm_fetch<TM>(g.X, g.sxk, g.sxm, 0, m0, g.K, g.M, tid, rx);
+  gemm_fetch<TN>(g.Y, g.syk, g.syn, 0, n0, g.K, g.N, tid, ry);
+  gemm_put<TM>(g.sxk, tid, rx, Xs[0]);
+  gemm_put<TN>(g.syk, tid, ry, Ys[0]);
   __syncthreads();
   const int nk = (g.K + GK - 1) / GK;
   for (int c = 0; c < nk; ++c) {
     const int buf = c & 1;
     const bool more = c + 1 < nk;
     if (more) {
-      gemm_fetch(g.X, g.sxk, g.sxm, (c + 1) * GK, m0, g.K, g.M, tid, rx);
-      gemm_fetch(g.Y, g.syk, g.syn, (c + 1) * GK, n0, g.K, g.N, tid, ry);
+      gemm_fetch<TM>(g.X, g.sxk, g.sxm, (c + 1) * GK, m0, g.K, g.M, tid, rx);
+      gemm_fetch<TN>(g.Y, g.syk, g.syn, (c + 1) * GK, n0, g.K, g.N, tid, ry);
     }
-#pragma unroll
+    // the large shape keeps one k-step's operands live at a time (its
+    // accumulators fill the accumulation registers)
+#pragma unroll(BI * BJ > 16 ? 1 : GK / 4)
     for (int s = 0; s < GK / 4; ++s) {
       const int kr = 4 * s + (lane >> 4);
-      double a[4], b[4];
+      double a[BI], b[BJ];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = Xs[buf][kr][wm + 16 * i + (lane & 15)];
+      for (int i = 0; i < BI; ++i) a[i] = Xs[buf][kr][wm + 16 * i + (lane & 15)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Ys[buf][kr][wn + 16 * j + (lane & 15)];
+      for (int j = 0; j < BJ; ++j) b[j] = Ys[buf][kr][wn + 16 * j + (lane & 15)];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < BI; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+        for (int j = 0; j < BJ; ++j)
           acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) {
       // the other buffer was last read in iteration c - 1, before its closing barrier
-      gemm_put(g.sxk, tid, rx, Xs[buf ^ 1]);
-      gemm_put(g.syk, tid, ry, Ys[buf ^ 1]);
+      gemm_put<TM>(g.sxk, tid, rx, Xs[buf ^ 1]);
+      gemm_put<TN>(g.syk, tid, ry, Ys[buf ^ 1]);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < BI; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < BJ; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int m = m0 + wm + 16 * i + 4 * r + (lane >> 4);
@@ -192,8 +202,15 @@ __global__ __launch_bounds__(256) void gemm_f64_kernel(GemmArgs g) {
 
 int gemm(const GemmArgs& a, hipStream_t st) {
   if (a.M <= 0 || a.N <= 0) return SYNIM_OK;
-  const dim3 grid((unsigned)((a.N + GT - 1) / GT), (unsigned)((a.M + GT - 1) / GT));
-  hipLaunchKernelGGL(gemm_f64_kernel, grid, dim3(256), 0, st, a);
+  // 256 x 128 tiles once there are enough of them to fill the CUs
+  const long big_tiles = (long)((a.M + 255) / 256) * ((a.N + 127) / 128);
+  if (big_tiles >= 256) {
+    const dim3 grid((unsigned)((a.N + 127) / 128), (unsigned)((a.M + 255) / 256));
+    hipLaunchKernelGGL((gemm_f64_kernel<8, 4>), grid, dim3(256), 0, st, a);
+  } else {
+    const dim3 grid((unsigned)((a.N + 127) / 128), (unsigned)((a.M + 127) / 128));
+    hipLaunchKernelGGL((gemm_f64_kernel<4, 4>), grid, dim3(256), 0, st, a);
+  }
   SYNIM_HIP_TRY(hipGetLastError());
   return SYNIM_OK;
 }

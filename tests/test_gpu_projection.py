@@ -2,7 +2,8 @@
 oracle, through the C ABI.
 
 * the FP64 MFMA GEMM on ragged sizes in both operand layouts, with alpha and
-  beta, against numpy's FP64 product (1e-12 of the result's maximum);
+  beta, in both tile shapes, against numpy's FP64 product (1e-12 of the
+  result's maximum);
 * the blocked Cholesky (lower factor against numpy's) and the two blocked
   triangular solves on a ragged SPD system (1e-10), and the not-positive-
   definite flag;
@@ -44,6 +45,48 @@ def test_gemm_f64_layouts(gpu_lib):
         S.gemm_f64(M, N, K, -0.5, dev(Xk), M, 1, dev(Yk), 1, K, 0.3, Cd, N)
         ref = -0.5 * Xk.T @ Yk.T + 0.3 * C0
         assert np.max(np.abs(Cd.cpu().numpy() - ref)) <= 1e-12 * np.abs(ref).max()
+
+
+def test_gemm_f64_large_tiles(gpu_lib):
+    """Products large enough for the 256 x 128 tile shape (at least 256 such
+    tiles), ragged in m, n and k, in both operand layouts."""
+    S = gpu_lib
+    rng = np.random.default_rng(11)
+    for M, N, K, k_unit in ((4100, 2060, 301, True), (4097, 2049, 37, False)):
+        say(f"[case] gemm large {M}x{N}x{K} k-unit-stride={k_unit}")
+        if k_unit:
+            Xm = rng.standard_normal((M, K))      # X(k, m) = Xm[m, k]: sxk = 1, sxm = K
+            Yn = rng.standard_normal((N, K))      # Y(k, n) = Yn[n, k]: syk = 1, syn = K
+            Cd = dev(np.zeros((M, N)))
+            S.gemm_f64(M, N, K, 1.0, dev(Xm), 1, K, dev(Yn), 1, K, 0.0, Cd, N)
+            ref = Xm @ Yn.T
+        else:
+            Xk = rng.standard_normal((K, M))      # sxk = M, sxm = 1
+            Yk = rng.standard_normal((K, N))      # syk = N, syn = 1
+            C0 = rng.standard_normal((M, N))
+            Cd = dev(C0)
+            S.gemm_f64(M, N, K, 0.75, dev(Xk), M, 1, dev(Yk), N, 1, -1.25, Cd, N)
+            ref = 0.75 * Xk.T @ Yk - 1.25 * C0
+        assert np.max(np.abs(Cd.cpu().numpy() - ref)) <= 1e-12 * np.abs(ref).max()
+
+
+def test_cholesky_large_trailing_updates(gpu_lib):
+    """A Cholesky factor large enough that its trailing lower-triangle updates
+    run in the 256 x 128 tile shape (tiles wholly above the diagonal skipped)."""
+    import torch
+    S = gpu_lib
+    rng = np.random.default_rng(12)
+    n = 4100
+    R = rng.standard_normal((n, 64))
+    A = R @ R.T + n * np.eye(n)
+    say("[case] potrf large", n)
+    Ad = dev(A)
+    st = torch.zeros(1, dtype=torch.int32, device="cuda")
+    S.potrf_f64(Ad, st)
+    assert int(st.item()) == 0
+    L = np.tril(Ad.cpu().numpy())
+    Lref = np.linalg.cholesky(A)
+    assert np.max(np.abs(L - Lref)) <= 1e-12 * np.abs(Lref).max()
 
 
 def test_cholesky_and_solves(gpu_lib):
