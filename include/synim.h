@@ -339,8 +339,9 @@ int synim_plan_oob(const void* ws, int64_t* host_count, void* stream);
  * of the IF-grid cells their weight patches start in, into full tiles whose
  * staged box fits the stage buffers, and one staging of a tile's IF rows
  * serves every WFS in it.  The tiles' staged boxes overlap by the patch halo,
- * so HBM still reads a DM's stack more than once (about 2.4 times for the
- * 6 x 3 MCAO system, against 7.7 times with one staging per pair).  Pairs may
+ * so HBM still reads a DM's stack more than once (about 3 times for the
+ * 6 x 3 MCAO system, against 7.7 times with one staging per pair; how many of
+ * the repeats the L2 absorbs depends on timing).  Pairs may
  * have their own map (cone effect, off-axis footprint), WFS (uneven
  * valid-subaperture counts) and DM (uneven actuator counts).  The maps live in
  * device memory, so a graph captured by synim_batch_run_graph replays after

@@ -472,12 +472,16 @@ __device__ int find_valid(const int32_t* __restrict__ valid, int nv, int k) {
 // holding a weight), or hr.x >= hr.y for an empty slot.  Writes rows[t*BHmax
 // + r], tile_info[t]; flags bit 1 of status[0] for a tile that does not fit,
 // counts non-empty tiles in status[1].  256 threads.
-// pitched: the rows are staged at one pitch per tile instead of packed, the
-// widest row's width rounded to 4 mod 8 floats, so that the lanes reading one
-// column of eight consecutive rows hit eight different LDS banks (packed rows
-// of varying widths start at offsets that collide).  Then rows[t*BHmax + r] =
-// (first column, width of row r) and tile_info[t].w = the pitch; the vectors
-// past a row's width are not fetched (the DMA zero-fills them).
+// pitched: the rows are staged at one pitch per tile instead of packed, in
+// one column frame: IF pixel (y, x) sits at (y - y0) * pitch + x - X0, X0 the
+// tile's leftmost staged column and the pitch the width of the tile's column
+// span rounded to 4 mod 8 floats.  Eight lanes reading one column of eight
+// consecutive rows then hit eight different LDS banks, and a lane's bank is
+// its subaperture's origin column mod 4 plus a multiple of 4 (packed rows of
+// varying widths, or rows that each start at their own first column, start
+// at offsets that collide).  Then tile_info[t] = (y0, rows, X0, pitch) and
+// rows[t*BHmax + r] = (first, end) of row r's staged columns relative to X0;
+// the vectors outside them are not fetched (the DMA zero-fills them).
 template <class SlotOf>
 __device__ __forceinline__ void build_tile_rows(int t, int NS, int PW, int BHmax, int cap_floats,
                                                 SlotOf slot_of, int2* rows_out, int4* tile_info,
@@ -549,20 +553,31 @@ __device__ __forceinline__ void build_tile_rows(int t, int NS, int PW, int BHmax
   }
   __syncthreads();
   if (pitched) {
-    __shared__ int s_pitch;
-    if (tid == 0) s_pitch = 0;
+    __shared__ int s_xa, s_xb;
+    if (tid == 0) {
+      s_xa = INT_MAX;
+      s_xb = INT_MIN;
+    }
     __syncthreads();
-    for (int r = tid; r < bh; r += blockDim.x) atomicMax(&s_pitch, s_w[r]);
-    __syncthreads();
-    const int pitch = (s_pitch & 4) == 0 ? s_pitch + 4 : s_pitch;   // 4 mod 8 floats
     for (int r = tid; r < bh; r += blockDim.x)
-      rows_out[(size_t)t * BHmax + r] = make_int2(s_x0[r], s_w[r]);
+      if (s_w[r] > 0) {
+        atomicMin(&s_xa, s_x0[r]);
+        atomicMax(&s_xb, s_x0[r] + s_w[r]);
+      }
+    __syncthreads();
+    // the rows of the slots' weights cover [y0, y0 + bh), so some row is
+    // non-empty; X0 and the span are multiples of 4
+    const int X0 = s_xa, span = s_xb - s_xa;
+    const int pitch = (span & 4) == 0 ? span + 4 : span;   // 4 mod 8 floats
+    for (int r = tid; r < bh; r += blockDim.x)
+      rows_out[(size_t)t * BHmax + r] =
+          s_w[r] > 0 ? make_int2(s_x0[r] - X0, s_x0[r] - X0 + s_w[r]) : make_int2(0, 0);
     if (tid == 0) {
       if ((long)bh * pitch > cap_floats) {
         atomicOr(status, 2);   // tile skipped: its slopes stay unwritten
         tile_info[t] = make_int4(0, 0, 0, 0);
       } else {
-        tile_info[t] = make_int4(y0, bh, bh * pitch, pitch);
+        tile_info[t] = make_int4(y0, bh, X0, pitch);
         atomicAdd(status + 1, 1);
       }
     }
@@ -779,6 +794,7 @@ int tiles_for_variant(const synim_wfs& w, const synim_affine& A, const Variant& 
   for (int ns = nslot_max; ns >= nslot_max / 4; ns /= 2)
     for (int tx = 1; tx <= ns; tx *= 2) {
       const int ty = ns / tx;
+      if (tx * ty != ns) continue;   // slot s sits at (s % tx, s / tx) of its tile
       int BW, BH;
       tile_bound(A, p, v, tx, ty, ph_need, &BW, &BH);
       if ((long)BH * BW > v.cap_floats() || BH > MAX_TILE_ROWS) continue;
@@ -1698,7 +1714,8 @@ int build_shared(synim_batch* b, const Variant& v) {
   }
   if (np >= (1 << 11)) return SYNIM_E_UNSUPPORTED;   // pair index field of a slot
   // staged-box bound of a tile whose origins span [x0, x1] x [y0, y1]: rows
-  // at one pitch, the widest row rounded to 4 mod 8 floats (+ 4)
+  // at one pitch, the column span of the patches (drift margin on both sides,
+  // ends at multiples of 4) rounded to 4 mod 8 floats (+ 4)
   auto box = [&](int x0, int x1, int y0, int y1, int* bw, int* bh) {
     *bw = (x1 - x0 + PW + 2 * SHARED_MARGIN + 3 + 3) / 4 * 4 + 4;
     *bh = y1 - y0 + PH + 2 * SHARED_MARGIN;
@@ -1779,16 +1796,46 @@ int build_shared(synim_batch* b, const Variant& v) {
   b->jorigin_host.clear();
   b->jgroups_host.assign(b->n_groups, make_int2(0, 0));
   int n_jt = 0, bh_max = 0;
+  // Slot order within a tile.  The lanes of half a wave (32 / LPS slots) read
+  // one column of their rows at the same time; a subaperture's rows, staged at
+  // a pitch of 4 mod 8 floats, spread its lanes over the banks of one residue
+  // mod 4, and that residue is its origin column's (the staged frame starts at
+  // a multiple of 4).  The slots are therefore dealt to the half-wave groups
+  // with the four residues as even as the tile's subapertures allow.
+  const int HW = std::max(1, 32 / v.LPS);
+  auto bank_order = [&](const Sl* in, size_t n) {
+    std::vector<Sl> cls[4];
+    for (size_t i = 0; i < n; ++i) cls[((in[i].ox % 4) + 4) % 4].push_back(in[i]);
+    size_t next[4] = {0, 0, 0, 0};
+    std::vector<Sl> out;
+    out.reserve(n);
+    while (out.size() < n) {
+      int used[4] = {0, 0, 0, 0};
+      for (int j = 0; j < HW && out.size() < n; ++j) {
+        int best = -1;
+        for (int c = 0; c < 4; ++c) {
+          const size_t left = cls[c].size() - next[c];
+          if (left == 0) continue;
+          if (best < 0 || used[c] < used[best] ||
+              (used[c] == used[best] && left > cls[best].size() - next[best]))
+            best = c;
+        }
+        out.push_back(cls[best][next[best]++]);
+        ++used[best];
+      }
+    }
+    return out;
+  };
   for (int gi = 0; gi < b->n_groups; ++gi) {
     std::vector<Sl> sl = per_group[gi];
     order_by_cells(sl, bx, by);
     b->jgroups_host[gi] = make_int2(n_jt, 0);
     pack(sl, [&](size_t t0, size_t t1, int, int bh) {
+      const std::vector<Sl> ts = bank_order(sl.data() + t0, t1 - t0);
       for (int s = 0; s < NS; ++s) {
-        const size_t at = t0 + s;
-        if (at < t1) {
-          b->jslots_host.push_back((sl[at].pair << 20) | sl[at].kk);
-          b->jorigin_host.push_back(make_int2(sl[at].ox, sl[at].oy));
+        if (s < (int)ts.size()) {
+          b->jslots_host.push_back((ts[s].pair << 20) | ts[s].kk);
+          b->jorigin_host.push_back(make_int2(ts[s].ox, ts[s].oy));
         } else {
           b->jslots_host.push_back(-1);
           b->jorigin_host.push_back(make_int2(INT_MIN, INT_MIN));

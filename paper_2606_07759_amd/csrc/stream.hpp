@@ -75,7 +75,7 @@ struct StreamArgs {
   // for all of them.
   const int* jslots;         // [tile][jNS]: (pair << 20) | subaperture, or -1; pair
                              // indexes the pair table
-  const int4* jinfo;         // [tile] (y0, rows, packed floats, 0), written by the plan
+  const int4* jinfo;         // [tile] (y0, rows, first column, pitch), written by the plan
   const int2* jrows;         // [tile][jBHmax] (first column, packed offset)
   const int2* jgroups;       // per DM group: (first shared tile, count)
   int jNS, jBHmax;
@@ -357,9 +357,13 @@ im_stream_kernel(StreamArgs g) {
     const size_t plane_in = (size_t)P.H_in * P.W_in;
     const int4 ti = shared ? g.jinfo[tile] : P.tile_info[tile];
     if (ti.y == 0) continue;   // empty tile
-    // ti.w > 0: rows staged at that pitch, row table (first column, width);
-    // else packed, row table (first column, packed offset)
-    const int y0 = ti.x, nfl = ti.z, pitch = ti.w;
+    // ti.w > 0: rows staged at that pitch from the tile's leftmost staged
+    // column ti.z (IF pixel (y, x) at (y - y0) * pitch + x - ti.z), row table
+    // (first, end) of each row's staged columns relative to ti.z;
+    // else packed, ti.z floats, row table (first column, packed offset)
+    const int y0 = ti.x, pitch = ti.w;
+    const int nfl = pitch > 0 ? ti.y * pitch : ti.z;
+    const int X0 = ti.z;
     // the tile's row table goes to LDS (one coalesced load), where the row
     // lookups below run without a memory round trip each
     {
@@ -399,13 +403,15 @@ im_stream_kernel(StreamArgs g) {
     int base[RPL];
 #pragma unroll
     for (int i = 0; i < RPL; ++i) {
-      // patch rows outside [hr.x, hr.y) hold zero weights and are not
-      // staged: point them at any staged float (all are finite)
-      const int pr = q + LPS * i;
+      // patch rows outside [hr.x, hr.y) hold zero weights and need not be
+      // staged: such a row reads the nearest one that is (finite values, and
+      // the address of another lane of the subaperture, which the LDS
+      // broadcasts instead of serialising a bank conflict)
+      const int pr = min(max(q + LPS * i, hr.x), hr.y - 1);
       base[i] = 0;
-      if (kk >= 0 && pr >= hr.x && pr < hr.y) {
-        const int2 rw = rows[o.y + pr - y0];
-        base[i] = (pitch > 0 ? (o.y + pr - y0) * pitch : rw.y) + (o.x - rw.x);
+      if (kk >= 0 && hr.x < hr.y) {
+        const int r = o.y + pr - y0;
+        base[i] = pitch > 0 ? r * pitch + (o.x - X0) : rows[r].y + (o.x - rows[r].x);
       }
     }
 
@@ -429,13 +435,15 @@ im_stream_kernel(StreamArgs g) {
       const int kp = KPMAX == 1 ? (fo < nfl ? 0 : 1) : (nfl > 0 ? fo / nfl : KP);
       if (kp < KP) {
         const int fr = fo - kp * nfl;          // offset within that actuator's rows
-        int lo, c;
+        int lo, gx;
         bool in_row = true;
         if (pitch > 0) {
-          // rows at one pitch: vectors past a row's width are not fetched
+          // rows at one pitch: vectors outside a row's staged columns are
+          // not fetched
           lo = fr / pitch;
-          c = fr - lo * pitch;
-          in_row = lo < ti.y && c < rows[lo].y;
+          const int c = fr - lo * pitch;
+          in_row = lo < ti.y && c >= rows[lo].x && c < rows[lo].y;
+          gx = X0 + c;
         } else {
           lo = 0;                              // last row whose offset is <= fr
           int hi = ti.y - 1;
@@ -443,10 +451,10 @@ im_stream_kernel(StreamArgs g) {
             const int mid = (lo + hi + 1) >> 1;
             if (rows[mid].y <= fr) lo = mid; else hi = mid - 1;
           }
-          c = fr - rows[lo].y;
+          gx = rows[lo].x + fr - rows[lo].y;
         }
         if (in_row) {
-          const int gx = rows[lo].x + c, gy = y0 + lo;
+          const int gy = y0 + lo;
           if (gx >= 0 && gx + VW <= P.W_in && gy >= 0 && gy < P.H_in)
             v = (unsigned)kp * (unsigned)plane_bytes + (unsigned)(gy * P.W_in + gx) * 4u;
         }
@@ -494,11 +502,30 @@ im_stream_kernel(StreamArgs g) {
         float sx = 0.f, sy = 0.f;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
+          if constexpr (BATCH) {
+            // a row's values are all read before its products, so that its
+            // LDS reads are in flight together (left alone, the scheduler
+            // issues each read just ahead of its two products and waits for
+            // it there, one LDS latency per pair of values).  The batch is
+            // bound by this contraction; the single-pair launches hide it
+            // behind the DMA and keep the compiler's order, which needs
+            // fewer registers.
+            float f[PW];
 #pragma unroll
-          for (int c = 0; c < PW; ++c) {
-            const float f = fk[base[i] + c];
-            sx = __fmaf_rn(wx[i][c], f, sx);
-            sy = __fmaf_rn(wy[i][c], f, sy);
+            for (int c = 0; c < PW; ++c) f[c] = fk[base[i] + c];
+            __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+            for (int c = 0; c < PW; ++c) {
+              sx = __fmaf_rn(wx[i][c], f[c], sx);
+              sy = __fmaf_rn(wy[i][c], f[c], sy);
+            }
+          } else {
+#pragma unroll
+            for (int c = 0; c < PW; ++c) {
+              const float f = fk[base[i] + c];
+              sx = __fmaf_rn(wx[i][c], f, sx);
+              sy = __fmaf_rn(wy[i][c], f, sy);
+            }
           }
         }
         sx = dpp_sum(sx, LPS);
