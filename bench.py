@@ -175,8 +175,9 @@ def _event_ms(fn, reps: int):
 
 
 def mcao_leg(synim, dev, reps: int = 10):
-    """Multi-WFS batch: 6 LGS WFS x 3 DMs (18 pair maps) in one persistent
-    launch, replayed as a hipGraph.  Algorithmic bytes: each DM's IF pixels
+    """Multi-WFS batch: 6 LGS WFS x 3 DMs (18 pair maps), one persistent
+    launch per patch size (the 15-deg and 45-deg clocked WFS need different
+    patches), replayed as a hipGraph.  Algorithmic bytes: each DM's IF pixels
     touched by the union of its 6 WFS footprints, read once, plus every
     pair's IM."""
     import numpy as np
@@ -190,6 +191,7 @@ def mcao_leg(synim, dev, reps: int = 10):
     B = synim.Batch(wfs, stacks, [(pr.wfs, pr.dm, A) for pr, A in zip(cfg.pairs, maps)], device=dev)
     tuned = B.autotune(6)
     cfg_b = B.config()
+    cfg_b["parts"] = B.parts()
     ms = _event_ms(B.run_graph, reps)
     if B.status() != 0:
         raise RuntimeError("MCAO batch plan status non-zero")
@@ -207,7 +209,7 @@ def mcao_leg(synim, dev, reps: int = 10):
     del stacks
     torch.cuda.empty_cache()
     return {"workload": "MCAO 6 LGS WFS x 3 DMs (81^2/47^2/37^2 on 512^2), 68x68 subap x 7 px, "
-                        "18 pair maps, one persistent launch (hipGraph replay)",
+                        "18 pair maps, one persistent launch per patch size (hipGraph replay)",
             "ms_per_batch": ms, "im_columns": cols, "columns_per_s": cols / (ms * 1e-3),
             "algorithmic_bytes": byts, "achieved_GBs": byts / (ms * 1e-3) / 1e9,
             "frac_of_hbm_peak": byts / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS,

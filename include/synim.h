@@ -347,7 +347,16 @@ int synim_plan_oob(const void* ws, int64_t* host_count, void* stream);
  * device memory, so a graph captured by synim_batch_run_graph replays after
  * synim_batch_set_maps without re-capture.  The kernel configuration is chosen
  * at creation from the initial maps; synim_batch_set_maps checks later maps
- * against it. */
+ * against it.
+ *
+ * Split by patch size: the one kernel variant of a launch runs, on every
+ * lane, the patch of the batch's most demanding pair (the WFS clocking and
+ * the cone scale set each pair's patch).  Where grouping the pairs by their
+ * own smallest patch cuts those products by at least 15% (weighted by
+ * subapertures x actuators), a shared-tile IM batch is split into parts, one
+ * per patch size, each with its own variant, tiles and launch, run one after
+ * the other on the caller's stream (synim_batch_parts gives their number);
+ * each part then stages a DM's rows for its own pairs. */
 
 typedef struct {
   const float* ifs;           /* device [n_act][H_in][W_in]                     */
@@ -386,11 +395,12 @@ int synim_batch_create(const synim_wfs* wfs, int n_wfs, const synim_dm* dms, int
  * (singular map), SYNIM_E_UNSUPPORTED, SYNIM_E_WORKSPACE, SYNIM_E_HIP. */
 int synim_batch_set_maps(synim_batch* b, const synim_affine* maps, void* stream);
 
-/* Enqueue the plans and the single stream launch of every pair. */
+/* Enqueue the plans and the single stream launch of every pair (one launch
+ * per part of a split batch). */
 int synim_batch_run(synim_batch* b, void* stream);
 
 /* As synim_batch_run, through a hipGraph captured on the first call (stream
- * must not be NULL) and replayed afterwards. */
+ * must not be NULL) and replayed afterwards (one graph per part). */
 int synim_batch_run_graph(synim_batch* b, void* stream);
 
 /* OR of the pairs' plan status words (see synim_plan_status); synchronises. */
@@ -403,14 +413,20 @@ int synim_batch_oob(synim_batch* b, int64_t* host_count, void* stream);
 
 /* Time up to max_variants kernel variants on the batch (each pair with its
  * best tile shape for that variant) and keep the fastest; drops a captured
- * graph.  times_ms (host) and n_tried (host) may be NULL.  Synchronises. */
+ * graph.  times_ms (host) and n_tried (host) may be NULL.  A split batch tunes
+ * each part on its own; times_ms[r] is then the sum of the parts' r-th
+ * variants (a part with fewer adds its last).  Synchronises. */
 int synim_batch_autotune(synim_batch* b, int max_variants, float* times_ms, int* n_tried,
                          void* stream);
 
 /* out6 (host) = block size, lanes per subaperture, pipeline stages, grid,
  * 16-byte DMA instructions per wave and stage, most actuators one stage
- * holds. */
+ * holds; of the first part for a batch split by patch size. */
 int synim_batch_config(const synim_batch* b, int* out6);
+
+/* *n_parts (host) = the launches one run of the batch makes: 1, or the number
+ * of patch-size parts of a split batch (see synim_batch_create). */
+int synim_batch_parts(const synim_batch* b, int* n_parts);
 
 /* Release the handle (the workspace stays the caller's). */
 void synim_batch_destroy(synim_batch* b);

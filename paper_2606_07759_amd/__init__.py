@@ -591,6 +591,12 @@ class Batch:
         return dict(block=o[0], lanes_per_subap=o[1], stages=o[2], grid=o[3],
                     dma_per_wave=o[4], pack=o[5])
 
+    def parts(self) -> int:
+        """Launches per run: 1, or the patch-size parts of a split batch."""
+        n = C.c_int(0)
+        _check(load().synim_batch_parts(self._h, C.byref(n)), "batch_parts")
+        return int(n.value)
+
     def close(self):
         if self._h and self._h.value:
             load().synim_batch_destroy(self._h)

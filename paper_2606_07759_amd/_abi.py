@@ -107,6 +107,7 @@ SIGNATURES = {
     "synim_batch_oob": (I, [P, C.POINTER(C.c_int64), P]),
     "synim_batch_autotune": (I, [P, I, C.POINTER(C.c_float), C.POINTER(I), P]),
     "synim_batch_config": (I, [P, C.POINTER(I)]),
+    "synim_batch_parts": (I, [P, C.POINTER(I)]),
     "synim_batch_destroy": (None, [P]),
     "synim_proj_rows": (I, [P, I, I, I, I, C.POINTER(I)]),
     "synim_proj_workspace": (I, [C.POINTER(SynimProjComponent), I, C.POINTER(SynimProjComponent),

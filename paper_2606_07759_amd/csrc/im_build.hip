@@ -1655,6 +1655,11 @@ struct synim_batch {
   std::vector<int2> jgroups_host;
   std::vector<int2> jorigin_host;             // per slot of jslots_host: the binned origin
   size_t off_jslots = 0, off_jinfo = 0, off_jrows = 0, off_jgroups = 0, off_jstatus = 0;
+  // A batch split by patch size (see batch_split): part k builds the pairs
+  // part_idx[k] with a kernel variant of its own, in its own launch; the
+  // batch itself then holds no tables.
+  std::vector<synim_batch*> parts;
+  std::vector<std::vector<int>> part_idx;
 };
 
 namespace synim {
@@ -2208,18 +2213,67 @@ int batch_pick_shared(synim_batch* b) {
   return SYNIM_OK;
 }
 
-}  // namespace
-}  // namespace synim
+// Smallest patch (PW * PH) of the variant table that holds a pair's patches,
+// 0 if none does.
+int min_patch_area(const synim_affine& A, int p) {
+  int pw, ph;
+  patch_need(A, p, &pw, &ph);
+  int best = 0;
+  for (int i = 0; i < num_variants(); ++i) {
+    const Variant& v = variants_table(nullptr)[i];
+    if (v.PW >= pw && v.PH() >= ph && (best == 0 || v.PW * v.PH() < best)) best = v.PW * v.PH();
+  }
+  return best;
+}
 
-extern "C" int synim_batch_workspace(const synim_wfs* wfs, int n_wfs, const synim_dm* dms,
-                                     int n_dm, const synim_pair* pairs, int n_pairs,
-                                     size_t* bytes) {
-  if (!bytes) return SYNIM_E_NULL;
-  int rc = batch_check(wfs, n_wfs, dms, n_dm, pairs, n_pairs);
-  if (rc != SYNIM_OK) return rc;
+// Parts of an IM batch by patch size.  Every lane of a tile runs the whole
+// patch of the batch's one kernel variant, sized for its most demanding pair;
+// where the pairs' own smallest patches would cut those FMAs by at least
+// kSplitGain (weighted by subapertures x actuators), the pairs are grouped by
+// that smallest patch, smallest first, and each group becomes a batch of its
+// own (its own variant, shared tiles and launch).  Only batches with shared
+// tiles split (IM planes, some DM seen by several pairs); the parts of a DM
+// then each stage its rows, so HBM reads them once per part.  Empty: no split.
+constexpr double kSplitGain = 0.15;
+std::vector<std::vector<int>> batch_split(const synim_wfs* wfs, const synim_dm* dms,
+                                          const synim_pair* pairs, int n_pairs) {
+  std::vector<int> per_dm(n_pairs, 0), area(n_pairs);
+  bool several = false;
+  for (int i = 0; i < n_pairs; ++i) several = several || ++per_dm[pairs[i].dm] > 1;
+  if (!several) return {};
+  int amax = 0;
+  for (int i = 0; i < n_pairs; ++i) {
+    area[i] = min_patch_area(pairs[i].A, wfs[pairs[i].wfs].p);
+    if (area[i] == 0) return {};
+    amax = std::max(amax, area[i]);
+  }
+  double whole = 0, split = 0;
+  for (int i = 0; i < n_pairs; ++i) {
+    const double w = (double)wfs[pairs[i].wfs].n_valid * dms[pairs[i].dm].n_act;
+    whole += w * amax;
+    split += w * area[i];
+  }
+  std::vector<int> areas(area);
+  std::sort(areas.begin(), areas.end());
+  areas.erase(std::unique(areas.begin(), areas.end()), areas.end());
+  if (areas.size() < 2 || split > (1.0 - kSplitGain) * whole) return {};
+  std::vector<std::vector<int>> out(areas.size());
+  for (int i = 0; i < n_pairs; ++i)
+    out[std::lower_bound(areas.begin(), areas.end(), area[i]) - areas.begin()].push_back(i);
+  return out;
+}
+
+std::vector<synim_pair> pairs_of(const synim_pair* pairs, const std::vector<int>& idx) {
+  std::vector<synim_pair> out;
+  for (int i : idx) out.push_back(pairs[i]);
+  return out;
+}
+
+int batch_workspace_whole(const synim_wfs* wfs, int n_wfs, const synim_dm* dms, int n_dm,
+                          const synim_pair* pairs, int n_pairs, size_t* bytes) {
   synim_batch b;
   batch_fill(&b, wfs, n_wfs, dms, n_dm, pairs, n_pairs);
-  rc = batch_pick_shared(&b);
+  int rc = batch_pick_shared(&b);
   if (rc != SYNIM_OK) return rc;
   size_t m = 0;
   for (int r = 0;; ++r) {
@@ -2233,6 +2287,29 @@ extern "C" int synim_batch_workspace(const synim_wfs* wfs, int n_wfs, const syni
   return SYNIM_OK;
 }
 
+}  // namespace
+}  // namespace synim
+
+extern "C" int synim_batch_workspace(const synim_wfs* wfs, int n_wfs, const synim_dm* dms,
+                                     int n_dm, const synim_pair* pairs, int n_pairs,
+                                     size_t* bytes) {
+  if (!bytes) return SYNIM_E_NULL;
+  int rc = batch_check(wfs, n_wfs, dms, n_dm, pairs, n_pairs);
+  if (rc != SYNIM_OK) return rc;
+  const auto parts = batch_split(wfs, dms, pairs, n_pairs);
+  if (parts.empty()) return batch_workspace_whole(wfs, n_wfs, dms, n_dm, pairs, n_pairs, bytes);
+  size_t total = 0;
+  for (const auto& idx : parts) {
+    const std::vector<synim_pair> sub = pairs_of(pairs, idx);
+    size_t m = 0;
+    rc = batch_workspace_whole(wfs, n_wfs, dms, n_dm, sub.data(), (int)sub.size(), &m);
+    if (rc != SYNIM_OK) return rc;
+    total += align_up(m, 256);
+  }
+  *bytes = total;
+  return SYNIM_OK;
+}
+
 extern "C" int synim_batch_create(const synim_wfs* wfs, int n_wfs, const synim_dm* dms, int n_dm,
                                   const synim_pair* pairs, int n_pairs, void* ws, size_t ws_bytes,
                                   void* stream, synim_batch** out) {
@@ -2240,6 +2317,32 @@ extern "C" int synim_batch_create(const synim_wfs* wfs, int n_wfs, const synim_d
   *out = nullptr;
   int rc = batch_check(wfs, n_wfs, dms, n_dm, pairs, n_pairs);
   if (rc != SYNIM_OK) return rc;
+  const auto parts = batch_split(wfs, dms, pairs, n_pairs);
+  if (!parts.empty()) {
+    // each part a whole batch on its own slice of the workspace
+    synim_batch* b = new synim_batch;
+    b->pairs.assign(pairs, pairs + n_pairs);
+    b->part_idx = parts;
+    size_t at = 0;
+    for (const auto& idx : parts) {
+      const std::vector<synim_pair> sub = pairs_of(pairs, idx);
+      size_t m = 0;
+      rc = batch_workspace_whole(wfs, n_wfs, dms, n_dm, sub.data(), (int)sub.size(), &m);
+      synim_batch* part = nullptr;
+      if (rc == SYNIM_OK && at + m > ws_bytes) rc = SYNIM_E_WORKSPACE;
+      if (rc == SYNIM_OK)
+        rc = synim_batch_create(wfs, n_wfs, dms, n_dm, sub.data(), (int)sub.size(),
+                                static_cast<char*>(ws) + at, m, stream, &part);
+      if (rc != SYNIM_OK) {
+        synim_batch_destroy(b);
+        return rc;
+      }
+      b->parts.push_back(part);
+      at += align_up(m, 256);
+    }
+    *out = b;
+    return SYNIM_OK;
+  }
   hipStream_t st = (hipStream_t)stream;
   synim_batch* b = new synim_batch;
   batch_fill(b, wfs, n_wfs, dms, n_dm, pairs, n_pairs);
@@ -2268,6 +2371,29 @@ extern "C" int synim_batch_create(const synim_wfs* wfs, int n_wfs, const synim_d
 
 extern "C" int synim_batch_set_maps(synim_batch* b, const synim_affine* maps, void* stream) {
   if (!b || !maps) return SYNIM_E_NULL;
+  if (!b->parts.empty()) {
+    // every map is checked before any part takes its maps: a singular map, or
+    // one whose patches outgrow its part's variant, leaves all parts as they
+    // were
+    for (size_t k = 0; k < b->parts.size(); ++k) {
+      const synim_batch* part = b->parts[k];
+      for (int i : b->part_idx[k]) {
+        const double det =
+            maps[i].A[0][0] * maps[i].A[1][1] - maps[i].A[0][1] * maps[i].A[1][0];
+        if (!(std::fabs(det) > 1e-12)) return SYNIM_E_PARAM;
+        int pw, ph;
+        patch_need(maps[i], part->wfs[b->pairs[i].wfs].p, &pw, &ph);
+        if (pw > part->var->PW || ph > part->var->PH()) return SYNIM_E_UNSUPPORTED;
+      }
+    }
+    for (size_t k = 0; k < b->parts.size(); ++k) {
+      std::vector<synim_affine> sub;
+      for (int i : b->part_idx[k]) sub.push_back(maps[i]);
+      const int rc = synim_batch_set_maps(b->parts[k], sub.data(), stream);
+      if (rc != SYNIM_OK) return rc;
+    }
+    return SYNIM_OK;
+  }
   hipStream_t st = (hipStream_t)stream;
   const int np = (int)b->pairs.size();
   // the previous upload must have left the staging buffer before it is reused
@@ -2317,12 +2443,22 @@ extern "C" int synim_batch_set_maps(synim_batch* b, const synim_affine* maps, vo
 
 extern "C" int synim_batch_run(synim_batch* b, void* stream) {
   if (!b) return SYNIM_E_NULL;
+  for (synim_batch* part : b->parts) {
+    const int rc = synim_batch_run(part, stream);
+    if (rc != SYNIM_OK) return rc;
+  }
+  if (!b->parts.empty()) return SYNIM_OK;
   return batch_enqueue(b, (hipStream_t)stream);
 }
 
 extern "C" int synim_batch_run_graph(synim_batch* b, void* stream) {
   if (!b) return SYNIM_E_NULL;
   if (!stream) return SYNIM_E_PARAM;   // capture needs an explicit stream
+  for (synim_batch* part : b->parts) {   // one graph per part
+    const int rc = synim_batch_run_graph(part, stream);
+    if (rc != SYNIM_OK) return rc;
+  }
+  if (!b->parts.empty()) return SYNIM_OK;
   hipStream_t st = (hipStream_t)stream;
   if (!b->exec) {
     SYNIM_HIP_TRY(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
@@ -2345,6 +2481,17 @@ extern "C" int synim_batch_run_graph(synim_batch* b, void* stream) {
 
 extern "C" int synim_batch_status(synim_batch* b, int* host_out, void* stream) {
   if (!b || !host_out) return SYNIM_E_NULL;
+  if (!b->parts.empty()) {
+    int v = 0;
+    for (synim_batch* part : b->parts) {
+      int x = 0;
+      const int rc = synim_batch_status(part, &x, stream);
+      if (rc != SYNIM_OK) return rc;
+      v |= x;
+    }
+    *host_out = v;
+    return SYNIM_OK;
+  }
   hipStream_t st = (hipStream_t)stream;
   std::vector<int> s(b->plans.size() + 1, 0);
   for (size_t i = 0; i < b->plans.size(); ++i)
@@ -2362,6 +2509,17 @@ extern "C" int synim_batch_status(synim_batch* b, int* host_out, void* stream) {
 
 extern "C" int synim_batch_oob(synim_batch* b, int64_t* host_count, void* stream) {
   if (!b || !host_count) return SYNIM_E_NULL;
+  if (!b->parts.empty()) {
+    int64_t t = 0;
+    for (synim_batch* part : b->parts) {
+      int64_t x = 0;
+      const int rc = synim_batch_oob(part, &x, stream);
+      if (rc != SYNIM_OK && rc != SYNIM_E_OOB) return rc;
+      t += x;
+    }
+    *host_count = t;
+    return t > 0 ? SYNIM_E_OOB : SYNIM_OK;
+  }
   hipStream_t st = (hipStream_t)stream;
   std::vector<int> n(b->plans.size(), 0);
   for (size_t i = 0; i < b->plans.size(); ++i)
@@ -2378,6 +2536,24 @@ extern "C" int synim_batch_autotune(synim_batch* b, int max_variants, float* tim
                                     int* n_tried, void* stream) {
   if (!b) return SYNIM_E_NULL;
   if (max_variants < 1) return SYNIM_E_PARAM;
+  if (!b->parts.empty()) {
+    // each part keeps its own fastest variant; times_ms[r] = the parts' r-th
+    // variants summed (a part with fewer variants adds its last time)
+    std::vector<float> sum(max_variants, 0.f);
+    int n_max = 0;
+    for (synim_batch* part : b->parts) {
+      std::vector<float> t(max_variants, 0.f);
+      int n = 0;
+      const int rc = synim_batch_autotune(part, max_variants, t.data(), &n, stream);
+      if (rc != SYNIM_OK) return rc;
+      for (int r = 0; r < max_variants; ++r) sum[r] += n > 0 ? t[std::min(r, n - 1)] : 0.f;
+      n_max = std::max(n_max, n);
+    }
+    if (times_ms)
+      for (int r = 0; r < n_max; ++r) times_ms[r] = sum[r];
+    if (n_tried) *n_tried = n_max;
+    return SYNIM_OK;
+  }
   hipStream_t st = (hipStream_t)stream;
   batch_drop_graph(b);
   hipEvent_t e0, e1;
@@ -2420,6 +2596,7 @@ extern "C" int synim_batch_autotune(synim_batch* b, int max_variants, float* tim
 }
 
 extern "C" int synim_batch_config(const synim_batch* b, int* out6) {
+  if (b && !b->parts.empty()) return synim_batch_config(b->parts[0], out6);
   if (!b || !out6 || !b->var) return SYNIM_E_NULL;
   out6[0] = b->var->BLOCK;
   out6[1] = b->var->LPS;
@@ -2430,8 +2607,15 @@ extern "C" int synim_batch_config(const synim_batch* b, int* out6) {
   return SYNIM_OK;
 }
 
+extern "C" int synim_batch_parts(const synim_batch* b, int* n_parts) {
+  if (!b || !n_parts) return SYNIM_E_NULL;
+  *n_parts = b->parts.empty() ? 1 : (int)b->parts.size();
+  return SYNIM_OK;
+}
+
 extern "C" void synim_batch_destroy(synim_batch* b) {
   if (!b) return;
+  for (synim_batch* part : b->parts) synim_batch_destroy(part);
   batch_drop_graph(b);
   if (b->staged) {
     (void)hipEventSynchronize(b->staged);

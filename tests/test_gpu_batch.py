@@ -7,6 +7,8 @@
   checked against the eager result; new maps uploaded to device memory and
   replayed without re-capture;
 * the batch autotuner keeps results within tolerance;
+* a batch split by patch size (one part per patch, each its own launch):
+  parity, graph replays, new maps, autotuning and refused maps;
 * the full 6 LGS x 3 DM MCAO workload on sampled columns of every pair.
 """
 import math
@@ -99,6 +101,78 @@ def test_small_batch_parity_and_graph(S):
         A = maps2[i]
         ref = oim.im_build(stacks_np[d], A[:, :2], A[:, 2], P, 5, v)
         assert rel_err(B.outs[i].cpu().numpy(), ref) <= IM_TOL, i
+    B.close()
+
+
+def split_system():
+    """2 WFS x 2 DMs whose pairs need different patches: WFS 0 unclocked behind
+    a 0.9 cone scale (8x8 patches), WFS 1 clocked by 45 deg (12x12)."""
+    wfs_np, grids, _ = small_system(seed=7)
+    pairs = []
+    for w, (rot, cone) in enumerate(((0.0, 0.9), (45.0, 1.0))):
+        for d in range(2):
+            pairs.append((w, d, wl.Geometry(cone_scale=cone, footprint_x=0.3 * d,
+                                             wfs_rot=math.radians(rot))))
+    return wfs_np[:2], grids, pairs
+
+
+def test_split_batch_by_patch_size(S):
+    """A batch whose pairs' patches differ enough runs as one part per patch
+    size: parity with the oracle, graph replays, new maps, the autotuner, and
+    a map that outgrows its part's patch refused."""
+    import torch
+    wfs_np, grids, pairs = split_system()
+    wfs = [S.Wfs.from_numpy(P, 5, v) for P, v in wfs_np]
+    stacks_np = [wl.if_stack(g) for g in grids]
+    stacks = [torch.from_numpy(F).cuda() for F in stacks_np]
+    maps = [S.affine_from_geometry(g, 80, 80, 60, 60) for (_, _, g) in pairs]
+    B = S.Batch(wfs, stacks, [(w, d, A) for (w, d, _), A in zip(pairs, maps)])
+    assert B.parts() == 2
+    outs = [o.clone() for o in B.run()]
+    torch.cuda.synchronize()
+    assert B.status() == 0
+    for i, (w, d, g) in enumerate(pairs):
+        P, v = wfs_np[w]
+        A = maps[i]
+        ref = oim.im_build(stacks_np[d], A[:, :2], A[:, 2], P, 5, v)
+        assert rel_err(outs[i].cpu().numpy(), ref) <= IM_TOL, (i, rel_err(outs[i].cpu().numpy(), ref))
+    for rep in range(3):
+        for o in B.outs:
+            o.fill_(-7.0)
+        B.run_graph()
+        torch.cuda.synchronize()
+        for i in range(len(pairs)):
+            assert torch.equal(B.outs[i], outs[i]), (rep, i)
+        junk = torch.randn(1 << 20, device="cuda").sum()
+        torch.cuda.synchronize()
+        del junk
+    maps2 = [S.affine_from_geometry(
+        wl.Geometry(cone_scale=g.cone_scale, footprint_x=g.footprint_x + 0.6,
+                    footprint_y=-0.5, wfs_rot=g.wfs_rot + 0.002), 80, 80, 60, 60)
+        for (_, _, g) in pairs]
+    B.set_maps(maps2)
+    B.run_graph()
+    torch.cuda.synchronize()
+    assert B.status() == 0
+    for i, (w, d, g) in enumerate(pairs):
+        P, v = wfs_np[w]
+        A = maps2[i]
+        ref = oim.im_build(stacks_np[d], A[:, :2], A[:, 2], P, 5, v)
+        assert rel_err(B.outs[i].cpu().numpy(), ref) <= IM_TOL, i
+    ref2 = [o.clone() for o in B.outs]
+    times = B.autotune(3)
+    assert len(times) >= 1 and all(t > 0 for t in times)
+    got = B.run()
+    torch.cuda.synchronize()
+    for a, b in zip(got, ref2):
+        assert torch.max(torch.abs(a - b)).item() <= IM_TOL * torch.max(torch.abs(b)).item()
+    # WFS 0's pairs clocked by 45 deg outgrow the 8x8 patches of their part
+    maps3 = [S.affine_from_geometry(
+        wl.Geometry(cone_scale=g.cone_scale, footprint_x=g.footprint_x, wfs_rot=math.radians(45.0)),
+        80, 80, 60, 60) for (_, _, g) in pairs]
+    with pytest.raises(S.SynimError) as ei:
+        B.set_maps(maps3)
+    assert ei.value.status == -8
     B.close()
 
 
