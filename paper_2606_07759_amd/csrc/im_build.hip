@@ -82,6 +82,7 @@ struct PlanJob {
   int4* tile_info;            // [tile] (y0, rows, packed floats, 0)
   int2* rows;                 // [tile][BHmax] (first column, packed offset)
   int* status;
+  int* counters;              // the stream kernel's work and sync counters
 };
 
 // The job of this workgroup.  TABLE = false: the one job passed by value, read
@@ -670,6 +671,15 @@ __global__ void zero_ints_kernel(int* __restrict__ p, int n) {
   if (i < n) p[i] = 0;
 }
 
+// A single plan's status words and the counters of the stream launch that
+// follows it, in the plan's first kernel launch.
+__global__ void zero_plan_kernel(int* __restrict__ status, int* __restrict__ counters,
+                                 int n_counters) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < 16) status[i] = 0;
+  if (i < n_counters) counters[i] = 0;
+}
+
 __global__ void zero_job_status_kernel(const PlanJob* __restrict__ jobs, int n) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n)
@@ -753,6 +763,11 @@ constexpr int MAX_PLANES = 5;
 // Counter ints of a plan: 8 work-item counters per plane, then one XCD sync
 // counter per plane and XCD, each on its own 128-byte line.
 constexpr int COUNTER_INTS = 8 * MAX_PLANES + 8 * MAX_PLANES * 32;
+// The finish count of a single-pair stream launch follows them, on a line of
+// its own; a plan clears all PLAN_COUNTER_INTS, and every stream launch on the
+// plan leaves them zero when it ends.
+constexpr int FINISH_INT = COUNTER_INTS + 32;
+constexpr int PLAN_COUNTER_INTS = FINISH_INT + 32;
 
 // Patch size (columns, rows) a map needs for subapertures of p pixels: the
 // haloed subaperture spans (p+1) output pixels, which the map stretches by
@@ -959,7 +974,7 @@ WsLayout layout(const synim_wfs& w, const Dims& d, int planes, bool repair = fal
   };
   const size_t nv = (size_t)w.n_valid;
   L.status = take(16 * sizeof(int));
-  L.counters = take(COUNTER_INTS * sizeof(int));   // work items, then sync blocks
+  L.counters = take(PLAN_COUNTER_INTS * sizeof(int));   // work items, sync blocks, finish
   L.scratch = take(64 * sizeof(float));
   L.origin = take(nv * sizeof(int2));
   L.hrows = take(nv * sizeof(int2));
@@ -1070,6 +1085,7 @@ PlanJob make_job(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map
   J.tile_info = P.tile_info();
   J.rows = P.rows();
   J.status = P.status();
+  J.counters = P.counters();
   return J;
 }
 
@@ -1123,7 +1139,8 @@ int enqueue_plans(const PlanJob& one, const PlanJob* jobs_dev, int n, int max_nv
     hipLaunchKernelGGL(zero_job_status_kernel, dim3((n + 255) / 256), dim3(256), 0, st, jobs_dev,
                        n);
   } else {
-    hipLaunchKernelGGL(zero_ints_kernel, dim3(1), dim3(64), 0, st, one.status, 16);
+    hipLaunchKernelGGL(zero_plan_kernel, dim3((PLAN_COUNTER_INTS + 255) / 256), dim3(256), 0,
+                       st, one.status, one.counters, PLAN_COUNTER_INTS);
   }
   SYNIM_HIP_TRY(hipGetLastError());
   if (jobs_dev)
@@ -1242,9 +1259,10 @@ int launch_stream(const Plan& P, const float* ifs, int n_act, int H_in, int W_in
   g.sync_every = d.sched == SCHED_XCD ? d.sync_every : 0;
   g.sync_ctr = P.counters() + 8 * MAX_PLANES;
   g.n_active = P.status() + 1;
-  hipLaunchKernelGGL(zero_ints_kernel, dim3((COUNTER_INTS + 255) / 256), dim3(256), 0, st,
-                     P.counters(), COUNTER_INTS);
-  SYNIM_HIP_TRY(hipGetLastError());
+  // the plan cleared the counters, and every launch on it clears them as it
+  // ends (its last workgroup)
+  g.finish = P.counters() + FINISH_INT;
+  g.n_counters = COUNTER_INTS;
   hipLaunchKernelGGL(fn, dim3((unsigned)G, 1, nplanes), dim3(v.BLOCK), 0, st, g);
   SYNIM_HIP_TRY(hipGetLastError());
   if (grid_out) *grid_out = G;

@@ -56,7 +56,7 @@ struct StreamArgs {
   const SuperChunk* recs;    // batched: per-XCD records, XCD x at recs[rec_off[x]..]
   const int2* groups;        // batched: per DM (first pair, number of pairs)
   int rec_off[8], rec_cnt[8], xcd_items[8];
-  int* counters;             // [gridDim.z][8] work counters, zeroed before the launch
+  int* counters;             // [gridDim.z][8] work counters, zero at the launch
   float* scratch;            // 64 floats that absorb the stores of idle lanes
   int plane0;                // first weight plane handled (blockIdx.z adds to it)
   int out_plane0;            // weight plane that lands in out[0]
@@ -67,7 +67,7 @@ struct StreamArgs {
   // its XCD has started the previous block, so the tiles of a chunk read the
   // rows they share within a few actuators of each other.  0 = off.
   int sync_every;
-  int* sync_ctr;             // [gridDim.z][8] block entries, zeroed before the launch
+  int* sync_ctr;             // [gridDim.z][8] block entries, zero at the launch
   const int* n_active;       // non-empty tiles (written by the plan)
   // Batched launches with shared tiles (nullptr jslots: per-pair tiles).  A
   // shared tile gathers the subapertures of every pair of one DM group whose
@@ -79,6 +79,12 @@ struct StreamArgs {
   const int2* jrows;         // [tile][jBHmax] (first column, packed offset)
   const int2* jgroups;       // per DM group: (first shared tile, count)
   int jNS, jBHmax;
+  // Single-pair launches: the last workgroup to finish sets the n_counters
+  // ints from `counters` (work and sync counters) and *finish back to zero,
+  // so the next launch on the same plan needs no clearing launch before it.
+  // nullptr: the caller clears the counters (batched launches).
+  int* finish;
+  int n_counters;
 };
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -638,6 +644,23 @@ im_stream_kernel(StreamArgs g) {
       double s = 0.0;
       for (int w = 0; w < BLOCK / 64; ++w) s += s_red[w];
       g.partials[(size_t)(plane - 1) * gridDim.x + blockIdx.x] = s;
+    }
+  }
+  if (g.finish != nullptr) {
+    // Every workgroup has taken its last item before it counts itself
+    // finished: its counter operations are device-scope atomics whose
+    // results it waited for, so they are performed before its finish count.
+    // The last one clears the counters with plain stores, which the end of
+    // the kernel makes visible to the next launch.  (No fence: a device-scope
+    // release here would write back the XCD's L2 at every workgroup's exit.)
+    __shared__ int s_last;
+    __syncthreads();
+    if (tid == 0)
+      s_last = atomicAdd(g.finish, 1) == (int)(gridDim.x * gridDim.y * gridDim.z) - 1;
+    __syncthreads();
+    if (s_last) {
+      for (int i = tid; i < g.n_counters; i += BLOCK) g.counters[i] = 0;
+      if (tid == 0) *g.finish = 0;
     }
   }
 }
