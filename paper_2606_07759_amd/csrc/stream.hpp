@@ -508,14 +508,15 @@ im_stream_kernel(StreamArgs g) {
         float sx = 0.f, sy = 0.f;
 #pragma unroll
         for (int i = 0; i < RPL; ++i) {
-          if constexpr (BATCH) {
+          if constexpr (BATCH || PW >= 12) {
             // a row's values are all read before its products, so that its
             // LDS reads are in flight together (left alone, the scheduler
-            // issues each read just ahead of its two products and waits for
-            // it there, one LDS latency per pair of values).  The batch is
-            // bound by this contraction; the single-pair launches hide it
-            // behind the DMA and keep the compiler's order, which needs
-            // fewer registers.
+            // may issue each read just ahead of its two products and wait for
+            // it there, one LDS latency per pair of values).  The batch, and
+            // wide patches (rotated or magnified maps), are bound by this
+            // contraction; the narrower single-pair patches hide it behind
+            // the DMA and keep the compiler's order, which needs fewer
+            // registers.
             float f[PW];
 #pragma unroll
             for (int c = 0; c < PW; ++c) f[c] = fk[base[i] + c];
