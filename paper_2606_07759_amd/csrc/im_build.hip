@@ -483,15 +483,26 @@ __device__ int find_valid(const int32_t* __restrict__ valid, int nv, int k) {
 // at offsets that collide).  Then tile_info[t] = (y0, rows, X0, pitch) and
 // rows[t*BHmax + r] = (first, end) of row r's staged columns relative to X0;
 // the vectors outside them are not fetched (the DMA zero-fills them).
+constexpr int MAX_SLOTS = 256;   // slots of a tile: block size / lanes per subaperture
 template <class SlotOf>
 __device__ __forceinline__ void build_tile_rows(int t, int NS, int PW, int BHmax, int cap_floats,
                                                 SlotOf slot_of, int2* rows_out, int4* tile_info,
                                                 int* status, bool pitched = false) {
-  __shared__ int s_ox[1024], s_oy[1024], s_oe[1024];
-  __shared__ int s_x0[MAX_TILE_ROWS], s_w[MAX_TILE_ROWS];
+  __shared__ int s_ox[MAX_SLOTS], s_oy[MAX_SLOTS], s_oe[MAX_SLOTS];
+  // per row: the slots' column span [s_lo, s_hi), then in place the staged
+  // first column (s_lo) and width (s_hi)
   __shared__ int s_lo[MAX_TILE_ROWS], s_hi[MAX_TILE_ROWS];
   __shared__ int s_ymin, s_ymax;
+  int* const s_x0 = s_lo;
+  int* const s_w = s_hi;
   const int tid = threadIdx.x;
+  if (NS > MAX_SLOTS) {
+    if (tid == 0) {
+      atomicOr(status, 2);   // tile skipped: its slopes stay unwritten
+      tile_info[t] = make_int4(0, 0, 0, 0);
+    }
+    return;
+  }
   if (tid == 0) {
     s_ymin = INT_MAX;
     s_ymax = INT_MIN;
