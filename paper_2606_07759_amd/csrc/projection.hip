@@ -233,8 +233,11 @@ constexpr int CB = 64;
 // One workgroup: the nb x nb diagonal block at (k, k), unblocked, in LDS.  A
 // pivot that is not positive sets *status (the matrix is not positive
 // definite) and the block is left as it is.
+// Linv (nullable): also writes the block's inverse L_kk^-1 there (CB x CB,
+// row-major, zero above the diagonal and outside nb x nb), each column by
+// forward substitution against the unit vector.
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, long ld, int k, int nb,
-                                                         int* status) {
+                                                         int* status, double* Linv = nullptr) {
   __shared__ double L[CB][CB + 1];
   __shared__ int bad;
   const int tid = threadIdx.x;
@@ -267,6 +270,21 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* A, long ld, int
     if (j <= i) A[(long)(k + i) * ld + k + j] = L[i][j];
   }
   if (tid == 0 && bad) atomicOr(status, 1);
+  if (Linv == nullptr) return;
+  __shared__ double X[CB][CB + 1];
+  for (int e = tid; e < CB * (CB + 1); e += 256) (&X[0][0])[e] = 0.0;
+  __syncthreads();
+  if (tid < nb) {
+    // column c = tid of L^-1: x_r = (delta_rc - sum_{c <= q < r} L[r][q] x_q) / L[r][r]
+    const int c = tid;
+    for (int r = c; r < nb; ++r) {
+      double v = r == c ? 1.0 : 0.0;
+      for (int q = c; q < r; ++q) v -= L[r][q] * X[q][c];
+      X[r][c] = v / L[r][r];
+    }
+  }
+  __syncthreads();
+  for (int e = tid; e < CB * CB; e += 256) Linv[e] = X[e / CB][e % CB];
 }
 
 // Panel rows i in [r0, n): row i of block column k becomes x with
@@ -413,6 +431,145 @@ int potrs(const double* L, int n, long ld, double* B, int m, long ldb, hipStream
     g.beta = 1.0;
     int rc = gemm(g, st);
     if (rc != SYNIM_OK) return rc;
+  }
+  return SYNIM_OK;
+}
+
+// dst[r][c] = src[r][c] for r < rows, c < cols (row-major, leading dimensions
+// lds, ldd).
+__global__ __launch_bounds__(256) void copy2d_kernel(const double* __restrict__ src, long lds,
+                                                     double* __restrict__ dst, long ldd,
+                                                     int rows, int cols) {
+  const long e = (long)blockIdx.x * 256 + threadIdx.x;
+  if (e >= (long)rows * cols) return;
+  const int r = (int)(e / cols), c = (int)(e - (long)r * cols);
+  dst[(long)r * ldd + c] = src[(long)r * lds + c];
+}
+
+int copy2d(const double* src, long lds, double* dst, long ldd, int rows, int cols,
+           hipStream_t st) {
+  const long n = (long)rows * cols;
+  if (n == 0) return SYNIM_OK;
+  hipLaunchKernelGGL(copy2d_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, src,
+                     lds, dst, ldd, rows, cols);
+  SYNIM_HIP_TRY(hipGetLastError());
+  return SYNIM_OK;
+}
+
+// Blocked Cholesky and solves with the diagonal blocks inverted: the panel
+// below each diagonal block and the block rows of the solves become matrix-
+// core GEMMs against L_kk^-1 instead of substitutions with one thread per row
+// or column.  Linv: ceil(n / CB) blocks of CB x CB doubles, written by potrf_inv
+// and read by potrs_inv; tmp: max(n, m) x CB doubles.
+int potrf_inv(double* A, int n, long ld, int* status, double* Linv, double* tmp,
+              hipStream_t st) {
+  for (int k = 0; k < n; k += CB) {
+    const int nb = std::min(CB, n - k);
+    double* Li = Linv + (long)(k / CB) * CB * CB;
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, A, ld, k, nb, status, Li);
+    SYNIM_HIP_TRY(hipGetLastError());
+    const int r0 = k + nb;
+    if (r0 >= n) break;
+    // panel: A[r0:, k:k+nb] <- A[r0:, k:k+nb] L_kk^-T (from a copy)
+    int rc = copy2d(A + (long)r0 * ld + k, ld, tmp, nb, n - r0, nb, st);
+    if (rc != SYNIM_OK) return rc;
+    GemmArgs p{};
+    p.M = n - r0;
+    p.N = nb;
+    p.K = nb;
+    p.X = tmp;   // X(q, i) = tmp[i][q]
+    p.sxk = 1;
+    p.sxm = nb;
+    p.Y = Li;    // Y(q, j) = L_kk^-1[j][q]
+    p.syk = 1;
+    p.syn = CB;
+    p.C = A + (long)r0 * ld + k;
+    p.ldc = ld;
+    p.alpha = 1.0;
+    p.beta = 0.0;
+    if ((rc = gemm(p, st)) != SYNIM_OK) return rc;
+    // trailing lower triangle: A[r0:, r0:] -= P P^T, P = A[r0:, k:k+nb]
+    GemmArgs g{};
+    g.M = g.N = n - r0;
+    g.K = nb;
+    g.X = g.Y = A + (long)r0 * ld + k;
+    g.sxk = g.syk = 1;
+    g.sxm = g.syn = ld;
+    g.C = A + (long)r0 * ld + r0;
+    g.ldc = ld;
+    g.alpha = -1.0;
+    g.beta = 1.0;
+    g.lower = 1;
+    if ((rc = gemm(g, st)) != SYNIM_OK) return rc;
+  }
+  return SYNIM_OK;
+}
+
+int potrs_inv(const double* L, int n, long ld, double* B, int m, long ldb, const double* Linv,
+              double* tmp, hipStream_t st) {
+  // B_k <- L_kk^-1 B_k (forward) or L_kk^-T B_k (backward), from a copy
+  auto diag = [&](int k, int nb, bool backward) {
+    int rc = copy2d(B + (long)k * ldb, ldb, tmp, m, nb, m, st);
+    if (rc != SYNIM_OK) return rc;
+    const double* Li = Linv + (long)(k / CB) * CB * CB;
+    GemmArgs d{};
+    d.M = nb;
+    d.N = m;
+    d.K = nb;
+    d.X = Li;   // X(q, i) = L^-1[i][q] (forward) or L^-1[q][i] (backward)
+    d.sxk = backward ? CB : 1;
+    d.sxm = backward ? 1 : CB;
+    d.Y = tmp;  // Y(q, c) = tmp[q][c]
+    d.syk = m;
+    d.syn = 1;
+    d.C = B + (long)k * ldb;
+    d.ldc = ldb;
+    d.alpha = 1.0;
+    d.beta = 0.0;
+    return gemm(d, st);
+  };
+  for (int k = 0; k < n; k += CB) {
+    const int nb = std::min(CB, n - k);
+    int rc = diag(k, nb, false);
+    if (rc != SYNIM_OK) return rc;
+    if (k + nb >= n) break;
+    GemmArgs g{};
+    g.M = n - k - nb;
+    g.N = m;
+    g.K = nb;
+    g.X = L + (long)(k + nb) * ld + k;
+    g.sxk = 1;
+    g.sxm = ld;
+    g.Y = B + (long)k * ldb;
+    g.syk = ldb;
+    g.syn = 1;
+    g.C = B + (long)(k + nb) * ldb;
+    g.ldc = ldb;
+    g.alpha = -1.0;
+    g.beta = 1.0;
+    if ((rc = gemm(g, st)) != SYNIM_OK) return rc;
+  }
+  const int last = ((n - 1) / CB) * CB;
+  for (int k = last; k >= 0; k -= CB) {
+    const int nb = std::min(CB, n - k);
+    int rc = diag(k, nb, true);
+    if (rc != SYNIM_OK) return rc;
+    if (k == 0) break;
+    GemmArgs g{};
+    g.M = k;
+    g.N = m;
+    g.K = nb;
+    g.X = L + (long)k * ld;
+    g.sxk = ld;
+    g.sxm = 1;
+    g.Y = B + (long)k * ldb;
+    g.syk = ldb;
+    g.syn = 1;
+    g.C = B;
+    g.ldc = ldb;
+    g.alpha = -1.0;
+    g.beta = 1.0;
+    if ((rc = gemm(g, st)) != SYNIM_OK) return rc;
   }
   return SYNIM_OK;
 }
@@ -655,8 +812,20 @@ extern "C" int synim_proj_opt(const synim_proj_component* dms, int n_dm,
   GemmArgs b{(int)ndm, (int)nl, (int)rows, pt_dm, 1, rows, pt_l, 1, rows, popt, nl, 1.0, 0.0, 0};
   if ((rc = gemm(b, st)) != SYNIM_OK) return rc;
   int* status = reinterpret_cast<int*>(w + L.status);
-  if ((rc = potrf(G, (int)ndm, ndm, status, st)) != SYNIM_OK) return rc;
-  if ((rc = potrs(G, (int)ndm, ndm, popt, (int)nl, nl, st)) != SYNIM_OK) return rc;
+  // the sampled matrices are spent: their memory holds the inverted diagonal
+  // blocks and the copies the solves work from
+  // (where they are too small, the substitution forms need no memory)
+  double* linv = pt_dm;
+  double* tmp = pt_dm + ((ndm + CB - 1) / CB) * CB * CB;
+  if ((size_t)(((ndm + CB - 1) / CB) * CB * CB + std::max(ndm, nl) * CB) <=
+      (size_t)rows * (size_t)ndm) {
+    if ((rc = potrf_inv(G, (int)ndm, ndm, status, linv, tmp, st)) != SYNIM_OK) return rc;
+    if ((rc = potrs_inv(G, (int)ndm, ndm, popt, (int)nl, nl, linv, tmp, st)) != SYNIM_OK)
+      return rc;
+  } else {
+    if ((rc = potrf(G, (int)ndm, ndm, status, st)) != SYNIM_OK) return rc;
+    if ((rc = potrs(G, (int)ndm, ndm, popt, (int)nl, nl, st)) != SYNIM_OK) return rc;
+  }
   // the host vectors must outlive the copies
   SYNIM_HIP_TRY(hipStreamSynchronize(st));
   int host_status = 0;

@@ -144,10 +144,21 @@ def test_projection_matrix_parity(gpu_lib, b):
     assert np.max(np.abs(got - ref)) <= 1e-12 * np.abs(ref).max()
 
 
-def test_popt_parity(gpu_lib):
-    S = gpu_lib
+def system_many_blocks():
+    """The same geometry with denser DMs: 586 DM bases, so the Cholesky and the
+    solves run over 9 diagonal blocks of 64 and a ragged last one."""
     dms, layers, dirs, pupil = system()
-    say("[case] P_opt")
+    g0 = wl.actuator_grid(19, 3.0, 56)
+    g1 = wl.actuator_grid(15, 4.3, 64)
+    dms = [(wl.if_stack(g0), 0.0, 0.5), (wl.if_stack(g1), 6000.0, 0.5)]
+    return dms, layers, dirs, pupil
+
+
+@pytest.mark.parametrize("many", [False, True])
+def test_popt_parity(gpu_lib, many):
+    S = gpu_lib
+    dms, layers, dirs, pupil = system_many_blocks() if many else system()
+    say(f"[case] P_opt, {sum(F.shape[0] for F, _, _ in dms)} DM bases")
     P_dm = opj.projection_matrix(dms, dirs, pupil, 0.5, 1)
     P_l = opj.projection_matrix(layers, dirs, pupil, 0.5, 1)
     lam = 1e-3 * np.trace(P_dm.T @ P_dm) / P_dm.shape[1]
