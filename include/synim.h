@@ -333,7 +333,8 @@ int synim_plan_oob(const void* ws, int64_t* host_count, void* stream);
 
 /* ------------------------------------------------------- multi-pair batch
  * Every (WFS, DM) pair of a multi-WFS system (e.g. 6 LGS WFS x 3 DMs) built in
- * one persistent launch - the multi-WFS batch of Sec. 4.2, where each DM's IF
+ * one persistent launch (one per patch size for a batch split as described
+ * below) - the multi-WFS batch of Sec. 4.2, where each DM's IF
  * stack is fetched once for all the WFS that see it.  For IM batches
  * (planes = 1) the subapertures of every WFS of a DM are packed, in the order
  * of the IF-grid cells their weight patches start in, into full tiles whose
