@@ -83,6 +83,10 @@ struct PlanJob {
   int2* rows;                 // [tile][BHmax] (first column, packed offset)
   int* status;
   int* counters;              // the stream kernel's work and sync counters
+  // [nv] pupil pixels of each subaperture, bit y*p + x (x, y within it), for
+  // p <= 8; null otherwise (the weights then read the pupil itself)
+  unsigned long long* submask;
+  MapD minv;                  // inverse of m's linear part (used when m_dev is null)
 };
 
 // The job of this workgroup.  TABLE = false: the one job passed by value, read
@@ -251,6 +255,12 @@ __global__ __launch_bounds__(PLAN_SUBAPS_BLOCK) void plan_subaps_kernel(
     nk += J.pupil[(size_t)y * W + x] ? 1 : 0;
   }
   for (int o = 32; o >= 1; o >>= 1) nk += __shfl_xor(nk, o, 64);
+  if (J.submask != nullptr) {
+    // lane i holds pixel (i % p, i / p) of the subaperture (p * p <= 64)
+    const bool in = lane < p * p && J.pupil[(size_t)(v * p + lane / p) * W + u * p + lane % p];
+    const unsigned long long mk = __ballot(in);
+    if (lane == 0) J.submask[kk] = mk;
+  }
   // samples this subaperture's central differences read (a non-zero c_x or
   // c_y) whose source point lies outside the IF grid: their bilinear taps
   // are zero-filled
@@ -307,8 +317,11 @@ __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long 
   const MapD m = J.m_dev ? *J.m_dev : J.m;
   const int p = J.p;
   // inverse of the linear part, for the window of candidate samples
-  const double det = m.a00 * m.a11 - m.a01 * m.a10;
-  const MapD inv{m.a11 / det, -m.a01 / det, -m.a10 / det, m.a00 / det, 0, 0};
+  MapD inv = J.minv;
+  if (J.m_dev) {
+    const double det = m.a00 * m.a11 - m.a01 * m.a10;
+    inv = MapD{m.a11 / det, -m.a01 / det, -m.a10 / det, m.a00 / det, 0, 0};
+  }
   const double rx = fabs(inv.a00) + fabs(inv.a01) + 0.01;
   const double ry = fabs(inv.a10) + fabs(inv.a11) + 0.01;
   const int kk = (int)(gid / E);
@@ -333,6 +346,15 @@ __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long 
   const int yl = max(max(v * p - 1 - pad, -1), (int)ceil(qy - ry));
   const int yh = min(min(v * p + p + pad, H), (int)floor(qy + ry));
   const int sx0 = u * p, sy0 = v * p;
+  // pixel (x, y) of the WFS grid is a pupil pixel of subaperture kk
+  const unsigned long long mk = J.submask ? J.submask[kk] : 0ull;
+  auto in_k = [&](int x, int y) -> int {
+    if (J.submask == nullptr) return in_sub(J.pupil, W, sx0, sy0, p, x, y);
+    return (x >= sx0 && x < sx0 + p && y >= sy0 && y < sy0 + p &&
+            ((mk >> ((y - sy0) * p + (x - sx0))) & 1ull))
+               ? 1
+               : 0;
+  };
   const int n_planes = MULTI ? J.n_planes : 1;
   Map4 dm{};
   if (MULTI && n_planes > 1) dm = J.dm_dev ? *J.dm_dev : J.dm;
@@ -350,9 +372,7 @@ __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long 
         for (int a2 = -1; a2 < p; ++a2) {     // position of the boundary along it
           const int x = comp == 0 ? sx0 + a2 : sx0 + a1;
           const int y = comp == 0 ? sy0 + a1 : sy0 + a2;
-          const int cc = comp == 0
-              ? in_sub(J.pupil, W, sx0, sy0, p, x, y) - in_sub(J.pupil, W, sx0, sy0, p, x + 1, y)
-              : in_sub(J.pupil, W, sx0, sy0, p, x, y) - in_sub(J.pupil, W, sx0, sy0, p, x, y + 1);
+          const int cc = comp == 0 ? in_k(x, y) - in_k(x + 1, y) : in_k(x, y) - in_k(x, y + 1);
           if (cc == 0) continue;
           const double px = comp == 0 ? x + 0.5 : (double)x;
           const double py = comp == 0 ? (double)y : y + 0.5;
@@ -378,8 +398,8 @@ __device__ __forceinline__ void plan_weight_entry(const PlanJob& J, int E, long 
         cx = ce[0];
         cy = ce[1];
       } else {
-        cx = in_sub(J.pupil, W, sx0, sy0, p, x - 1, y) - in_sub(J.pupil, W, sx0, sy0, p, x + 1, y);
-        cy = in_sub(J.pupil, W, sx0, sy0, p, x, y - 1) - in_sub(J.pupil, W, sx0, sy0, p, x, y + 1);
+        cx = in_k(x - 1, y) - in_k(x + 1, y);
+        cy = in_k(x, y - 1) - in_k(x, y + 1);
       }
       if (cx == 0.0 && cy == 0.0) continue;
       double xs, ys;
@@ -767,7 +787,7 @@ struct Dims {
 
 struct WsLayout {
   size_t status, counters, scratch, origin, hrows, inv2nk, weights, slot_kk, tile_info, rows,
-      partials, core, ceff, total;
+      partials, core, ceff, submask, total;
 };
 
 constexpr int MAX_PLANES = 5;
@@ -998,6 +1018,7 @@ WsLayout layout(const synim_wfs& w, const Dims& d, int planes, bool repair = fal
   const size_t rw = (size_t)sample_window(w.p, true);
   L.core = take(repair ? (size_t)(w.n_sub_x * w.p + 2) * (w.n_sub_y * w.p + 2) : 0);
   L.ceff = take(repair ? nv * rw * rw * 2 * sizeof(double) : 0);
+  L.submask = take(nv * sizeof(unsigned long long));
   L.total = off;
   return L;
 }
@@ -1019,6 +1040,9 @@ struct Plan {
   double* partials() const { return reinterpret_cast<double*>(ws + L.partials); }
   uint8_t* core() const { return reinterpret_cast<uint8_t*>(ws + L.core); }
   double* ceff() const { return reinterpret_cast<double*>(ws + L.ceff); }
+  unsigned long long* submask() const {
+    return reinterpret_cast<unsigned long long*>(ws + L.submask);
+  }
 };
 
 // Largest workspace any candidate configuration of this geometry needs, so a
@@ -1097,6 +1121,9 @@ PlanJob make_job(const synim_wfs& w, const MapD& m, const MapD* m_dev, const Map
   J.rows = P.rows();
   J.status = P.status();
   J.counters = P.counters();
+  J.submask = w.p <= 8 ? P.submask() : nullptr;
+  const double det = m.a00 * m.a11 - m.a01 * m.a10;
+  J.minv = MapD{m.a11 / det, -m.a01 / det, -m.a10 / det, m.a00 / det, 0, 0};
   return J;
 }
 
