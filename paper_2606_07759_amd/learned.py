@@ -116,11 +116,21 @@ class Trained:
 
 
 def train(system: ProbeSystem, slopes, theta, *, feat_len=4000, epochs=60, batch=256, lr=1e-3,
-          lr_min=1e-5, seed=0, val_frac=0.1, patience=12, log=None) -> Trained:
+          lr_min=1e-5, seed=0, val_frac=0.1, patience=12, log=None,
+          checkpoint: Optional[str] = None, resume: Optional[str] = None,
+          stop_after: Optional[int] = None) -> Trained:
     """Train the estimator on (noisy slopes [n][M] GPU, theta [n][4] numpy).
 
     Adam with a cosine learning-rate decay from ``lr`` to ``lr_min`` over the
-    epochs; the parameters with the best validation MSE are kept."""
+    epochs; the parameters with the best validation MSE are kept.
+
+    ``checkpoint``: a ``.npz`` path written after every epoch with the
+    parameters, the Adam moments and step, the best parameters so far, the
+    early-stop state, the history and the state of the shuffling generator.
+    ``resume``: such a file; training continues after its last epoch, and with
+    the same data and settings ends where an uninterrupted run would (the
+    kernels reduce in a fixed order).  ``stop_after``: leave after that many
+    epochs of this call (an interrupted run, for tests)."""
     import torch
     dev = slopes.device
     net = net_for(system, feat_len)
@@ -146,8 +156,25 @@ def train(system: ProbeSystem, slopes, theta, *, feat_len=4000, epochs=60, batch
     loss = torch.zeros(1, dtype=torch.float32, device=dev)
     g = torch.Generator(device="cpu").manual_seed(seed)
     best, best_params, bad, step, hist = float("inf"), params.clone(), 0, 0, []
+    ep0 = 0
+    if resume is not None:
+        with np.load(resume, allow_pickle=False) as z:
+            if int(z["n_params"]) != params.numel():
+                raise ValueError("checkpoint is for another network")
+            params.copy_(torch.from_numpy(z["params"]))
+            m.copy_(torch.from_numpy(z["m"]))
+            v.copy_(torch.from_numpy(z["v"]))
+            best_params = torch.from_numpy(z["best_params"]).to(dev)
+            best, bad, step = float(z["best"]), int(z["bad"]), int(z["step"])
+            hist = [tuple(r) for r in z["history"].tolist()]
+            ep0 = int(z["epoch"]) + 1
+            g.set_state(torch.from_numpy(z["rng_state"]))
     t0 = time.perf_counter()
-    for ep in range(epochs):
+    done = 0
+    for ep in range(ep0, epochs):
+        if stop_after is not None and done >= stop_after:
+            break
+        done += 1
         perm = torch.randperm(n_tr, generator=g).to(dev)
         tot = 0.0
         nb = n_tr // batch
@@ -171,11 +198,43 @@ def train(system: ProbeSystem, slopes, theta, *, feat_len=4000, epochs=60, batch
             best, best_params, bad = vl, params.clone(), 0
         else:
             bad += 1
-            if bad >= patience:
-                break
+        if checkpoint is not None:
+            np.savez(checkpoint, params=params.cpu().numpy(), m=m.cpu().numpy(),
+                     v=v.cpu().numpy(), best_params=best_params.cpu().numpy(),
+                     best=np.float64(best), bad=np.int64(bad), step=np.int64(step),
+                     epoch=np.int64(ep), history=np.array(hist, dtype=np.float64).reshape(-1, 3),
+                     rng_state=g.get_state().numpy(), n_params=np.int64(params.numel()))
+        if bad >= patience:
+            break
     torch.cuda.synchronize()
     return Trained(net, best_params, mean.contiguous(), std.contiguous(), feat_len, hist,
                    time.perf_counter() - t0)
+
+
+def save_trained(path: str, trained: Trained) -> None:
+    """The trained estimator (network shape, parameters, feature mean and std)
+    as a ``.npz`` file."""
+    d = trained.net.desc
+    np.savez(path, params=trained.params.cpu().numpy(), mean=trained.mean.cpu().numpy(),
+             std=trained.std.cpu().numpy(), feat_len=np.int64(trained.feat_len),
+             shape=np.array([d.n_in, d.h1, d.h2, d.n_out, d.seg0, d.len0, d.seg1, d.len1],
+                            dtype=np.int64),
+             history=np.array(trained.history, dtype=np.float64).reshape(-1, 3),
+             seconds=np.float64(trained.seconds))
+
+
+def load_trained(path: str, device="cuda") -> Trained:
+    """A trained estimator saved by :func:`save_trained`, on ``device``."""
+    import torch
+    with np.load(path, allow_pickle=False) as z:
+        n_in, h1, h2, n_out, s0, l0, s1, l1 = (int(x) for x in z["shape"])
+        net = Mlp(n_in, h1, h2, n_out, ((s0, l0), (s1, l1)))
+        params = torch.from_numpy(z["params"]).to(device)
+        if params.numel() != net.n_params:
+            raise ValueError("parameter count does not match the network shape")
+        return Trained(net, params, torch.from_numpy(z["mean"]).to(device),
+                       torch.from_numpy(z["std"]).to(device), int(z["feat_len"]),
+                       [tuple(r) for r in z["history"].tolist()], float(z["seconds"]))
 
 
 def estimator(system: ProbeSystem, trained: Optional[Trained], max_batch: int,
