@@ -312,6 +312,21 @@ int synim_im_set_config(const synim_wfs* wfs, const synim_affine* A, const int* 
 /* Forget every autotuned configuration. */
 void synim_autotune_clear(void);
 
+/* The autotune cache as a flat int32 record, to keep across processes (the
+ * configurations measured fastest, keyed by geometry; the record is tied to
+ * this library's kernel-variant table).  out (host, [cap]) may be NULL:
+ * *n_ints (host) then receives the length needed.  Errors: SYNIM_E_NULL,
+ * SYNIM_E_SHAPE (cap too small). */
+int synim_autotune_export(int32_t* out, int cap, int* n_ints);
+
+/* Merge a record written by synim_autotune_export into the cache (entries
+ * replace those of the same geometry).  A configuration that is no longer a
+ * candidate of its geometry is ignored when looked up.  Errors: SYNIM_E_NULL,
+ * SYNIM_E_PARAM (not such a record, or a malformed entry), SYNIM_E_SHAPE
+ * (length), SYNIM_E_UNSUPPORTED (written by a library with another variant
+ * table), SYNIM_E_WORKSPACE (cache full: 256 geometries). */
+int synim_autotune_import(const int32_t* in, int n_ints);
+
 /* Device status word of the last plan built in `ws`: bit 0 a weight patch was
  * too small for the map, bit 1 a tile bounding box overflowed (that tile's
  * slopes are not written), bit 2 a valid subaperture has no pupil pixel (its

@@ -378,6 +378,46 @@ def autotune_clear():
     load().synim_autotune_clear()
 
 
+def autotune_export() -> list:
+    """The autotune cache as a list of ints (see ``synim_autotune_export``)."""
+    lib = load()
+    n = C.c_int(0)
+    _check(lib.synim_autotune_export(None, 0, C.byref(n)), "autotune_export")
+    buf = (C.c_int32 * max(1, n.value))()
+    _check(lib.synim_autotune_export(buf, n.value, C.byref(n)), "autotune_export")
+    return [int(buf[i]) for i in range(n.value)]
+
+
+def autotune_import(record) -> None:
+    """Merge a record from :func:`autotune_export` into the cache."""
+    rec = [int(x) for x in record]
+    buf = (C.c_int32 * max(1, len(rec)))(*rec)
+    _check(load().synim_autotune_import(buf, len(rec)), "autotune_import")
+
+
+def autotune_save(path: str, device_name: str = "") -> None:
+    """Write the autotune cache to a JSON file (with the device it was measured
+    on, as given)."""
+    import json
+    with open(path, "w") as f:
+        json.dump({"format": 1, "device": device_name, "record": autotune_export()}, f)
+
+
+def autotune_load(path: str, device_name: str = "") -> bool:
+    """Merge a cache written by :func:`autotune_save`; False (nothing merged)
+    when it was measured on another device than ``device_name`` (when both
+    are given)."""
+    import json
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("format") != 1:
+        raise ValueError("not an autotune cache file")
+    if device_name and d.get("device") and d["device"] != device_name:
+        return False
+    autotune_import(d["record"])
+    return True
+
+
 def plan_status(ws) -> int:
     """Device status word of the last plan built in ``ws`` (synchronises)."""
     lib = load()

@@ -96,6 +96,8 @@ SIGNATURES = {
                               I, C.POINTER(C.c_float), C.POINTER(I), P]),
     "synim_im_config": (I, [C.POINTER(SynimWfs), C.POINTER(SynimAffine), C.POINTER(I)]),
     "synim_autotune_clear": (None, []),
+    "synim_autotune_export": (I, [C.POINTER(C.c_int32), I, C.POINTER(I)]),
+    "synim_autotune_import": (I, [C.POINTER(C.c_int32), I]),
     "synim_batch_workspace": (I, [C.POINTER(SynimWfs), I, C.POINTER(SynimDm), I,
                                   C.POINTER(SynimPair), I, C.POINTER(SZ)]),
     "synim_batch_create": (I, [C.POINTER(SynimWfs), I, C.POINTER(SynimDm), I,

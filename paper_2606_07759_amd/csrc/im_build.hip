@@ -1454,6 +1454,105 @@ extern "C" void synim_autotune_clear(void) {
   g_tune_n = 0;
 }
 
+namespace synim {
+namespace {
+// Autotune cache records: a header (format, variant-table signature, entry
+// count), then per entry the geometry key (n_sub_x, n_sub_y, p, n_valid, the
+// four rounded map entries as high/low 32-bit halves) and the configuration
+// (variant index, TX, TY, NSLOT, schedule, sync blocks).
+constexpr int TUNE_FORMAT = 1, TUNE_HEADER = 3, TUNE_ENTRY = 4 + 8 + 6;
+
+// FNV-1a over every variant's parameters: a record names variants by their
+// index in the table, so it is only valid for the same table.
+int32_t variant_signature() {
+  uint32_t h = 2166136261u;
+  auto mix = [&](int v) {
+    for (int b = 0; b < 4; ++b) {
+      h ^= (uint32_t)((v >> (8 * b)) & 0xff);
+      h *= 16777619u;
+    }
+  };
+  const int n = num_variants();
+  mix(n);
+  for (int i = 0; i < n; ++i) {
+    const Variant& v = variants_table(nullptr)[i];
+    for (int x : {v.BLOCK, v.LPS, v.RPL, v.PW, v.NJ4, v.NST, v.PACK}) mix(x);
+  }
+  return (int32_t)h;
+}
+}  // namespace
+}  // namespace synim
+
+extern "C" int synim_autotune_export(int32_t* out, int cap, int* n_ints) {
+  if (!n_ints) return SYNIM_E_NULL;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  const int need = TUNE_HEADER + TUNE_ENTRY * g_tune_n;
+  *n_ints = need;
+  if (!out) return SYNIM_OK;
+  if (cap < need) return SYNIM_E_SHAPE;
+  out[0] = TUNE_FORMAT;
+  out[1] = variant_signature();
+  out[2] = g_tune_n;
+  for (int i = 0; i < g_tune_n; ++i) {
+    int32_t* o = out + TUNE_HEADER + TUNE_ENTRY * i;
+    const TuneEntry& e = g_tune[i];
+    o[0] = e.key.n_sub_x;
+    o[1] = e.key.n_sub_y;
+    o[2] = e.key.p;
+    o[3] = e.key.n_valid;
+    for (int j = 0; j < 4; ++j) {
+      const uint64_t a = (uint64_t)e.key.a[j];
+      o[4 + 2 * j] = (int32_t)(uint32_t)(a >> 32);
+      o[5 + 2 * j] = (int32_t)(uint32_t)(a & 0xffffffffu);
+    }
+    o[12] = e.variant;
+    o[13] = e.TX;
+    o[14] = e.TY;
+    o[15] = e.NSLOT;
+    o[16] = e.sched;
+    o[17] = e.sync_every;
+  }
+  return SYNIM_OK;
+}
+
+extern "C" int synim_autotune_import(const int32_t* in, int n_ints) {
+  if (!in) return SYNIM_E_NULL;
+  if (n_ints < TUNE_HEADER || in[0] != TUNE_FORMAT) return SYNIM_E_PARAM;
+  const int n = in[2];
+  if (n < 0 || n_ints != TUNE_HEADER + TUNE_ENTRY * n) return SYNIM_E_SHAPE;
+  if (in[1] != variant_signature()) return SYNIM_E_UNSUPPORTED;
+  std::vector<TuneEntry> es;
+  for (int i = 0; i < n; ++i) {
+    const int32_t* r = in + TUNE_HEADER + TUNE_ENTRY * i;
+    TuneEntry e{};
+    e.key.n_sub_x = r[0];
+    e.key.n_sub_y = r[1];
+    e.key.p = r[2];
+    e.key.n_valid = r[3];
+    for (int j = 0; j < 4; ++j)
+      e.key.a[j] = (long long)(((uint64_t)(uint32_t)r[4 + 2 * j] << 32) | (uint32_t)r[5 + 2 * j]);
+    e.variant = r[12];
+    e.TX = r[13];
+    e.TY = r[14];
+    e.NSLOT = r[15];
+    e.sched = r[16];
+    e.sync_every = r[17];
+    if (e.variant < 0 || e.variant >= num_variants() || e.TX < 1 || e.TY < 1 || e.NSLOT < 1 ||
+        (e.sched != SCHED_DYNAMIC && e.sched != SCHED_XCD) || e.sync_every < 0)
+      return SYNIM_E_PARAM;
+    es.push_back(e);
+  }
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  for (const TuneEntry& e : es) {
+    int i = 0;
+    while (i < g_tune_n && !(g_tune[i].key == e.key)) ++i;
+    if (i < g_tune_n) g_tune[i] = e;
+    else if (g_tune_n < 256) g_tune[g_tune_n++] = e;
+    else return SYNIM_E_WORKSPACE;
+  }
+  return SYNIM_OK;
+}
+
 extern "C" int synim_im_build(const float* ifs, int n_act, int H_in, int W_in,
                               const synim_affine* A, const synim_wfs* wfs, float* im, void* ws,
                               size_t ws_bytes, void* stream) {

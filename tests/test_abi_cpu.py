@@ -144,3 +144,60 @@ def test_argument_validation_before_device_work(lib):
                                  0x30, 1 << 20, None) == -1
     assert lib.synim_im_apply(0x10, 4, 96, 96, C.byref(A), C.byref(w), 1, 1, 0x20, 0x30,
                               1 << 20, None) == -3
+
+
+def test_autotune_cache_round_trip(lib, tmp_path):
+    """The autotune cache leaves the process as a record / JSON file and comes
+    back: a pinned configuration survives clear + load; a record of another
+    variant table, a malformed one, or one measured on another device is not
+    taken."""
+    import paper_2606_07759_amd as S
+    from paper_2606_07759_amd import _abi
+    A = _abi.SynimAffine()
+    A.A[0][0] = A.A[1][1] = 1.0
+    A.A[0][1] = 0.01
+    w = _fake_wfs()
+    S.autotune_clear()
+    rec = S.autotune_export()
+    assert len(rec) == 3 and rec[0] == 1 and rec[2] == 0
+    NC = 10
+    cands = (C.c_int * (256 * NC))()
+    n = C.c_int(0)
+    assert lib.synim_im_candidates(C.byref(w), C.byref(A), cands, 256, C.byref(n)) == 0
+    assert n.value >= 2
+    first = list(cands[0:NC])
+    last = list(cands[(n.value - 1) * NC:n.value * NC])
+    assert first != last
+    assert lib.synim_im_set_config(C.byref(w), C.byref(A), (C.c_int * NC)(*last)) == 0
+    cfg = (C.c_int * NC)()
+
+    def current():
+        assert lib.synim_im_config(C.byref(w), C.byref(A), cfg) == 0
+        return list(cfg)
+
+    assert current() == last
+    rec = S.autotune_export()
+    assert len(rec) == 3 + 18 and rec[2] == 1
+    path = str(tmp_path / "tune.json")
+    S.autotune_save(path, "device A")
+    S.autotune_clear()
+    assert current() == first
+    assert not S.autotune_load(path, "device B")
+    assert current() == first
+    assert S.autotune_load(path, "device A")
+    assert current() == last
+    S.autotune_clear()
+    bad = list(rec)
+    bad[1] ^= 1                              # another variant table
+    with pytest.raises(S.SynimError) as e:
+        S.autotune_import(bad)
+    assert e.value.status == -8
+    with pytest.raises(S.SynimError) as e:
+        S.autotune_import(rec[:-1])          # truncated
+    assert e.value.status == -2
+    bad = list(rec)
+    bad[3 + 12] = 10 ** 6                    # no such variant
+    with pytest.raises(S.SynimError) as e:
+        S.autotune_import(bad)
+    assert e.value.status == -3
+    assert current() == first
