@@ -392,6 +392,48 @@ def misreg_leg(n_train: int, n_eval: int, epochs: int):
     return rep
 
 
+def schedules_leg(index: int = -1, reps: int = 10):
+    """The ELT stream kernel under its two schedules: every one-chunk-per-XCD
+    candidate and the dynamic candidates of the same tile shapes, each pinned,
+    planned and timed over `reps` launches (HIP events on the launch stream).
+    index >= 0 runs only that entry of the list (for a counter pass)."""
+    import torch
+    import paper_2606_07759_amd as synim
+    import workloads as wl
+    synim.load()
+    dev = torch.device("cuda:0")
+    cfg = wl.scao_elt(0)
+    Fd = wl.if_stack_torch(cfg.grid, dev)
+    A, _ = synim.affine_from_misreg(cfg.theta, 512, 512, cfg.n_out, cfg.n_out)
+    wfs = synim.Wfs.from_numpy(cfg.pupil, cfg.p, cfg.valid, device=dev)
+    launch_bytes = cfg.grid.n_act * (4 * touched_if_pixels(cfg, A) + 8 * cfg.n_valid)
+    shape = lambda c: tuple(c[k] for k in synim._CFG_KEYS if k != "schedule")
+    cands = synim.im_candidates(wfs, A)
+    xcd_shapes = {shape(c) for c in cands if c["schedule"] != 0}
+    sel = [c for c in cands if shape(c) in xcd_shapes]
+    ws = torch.empty(synim.im_workspace_bytes(wfs, A, 1), dtype=torch.uint8, device=dev)
+    out = torch.empty((cfg.grid.n_act, 2 * cfg.n_valid), dtype=torch.float32, device=dev)
+    st = torch.cuda.current_stream()
+    for i, c in enumerate(sel):
+        if index >= 0 and i != index:
+            continue
+        synim.im_set_config(wfs, A, c)
+        synim.im_plan(wfs, A, ws=ws, grid=(cfg.grid.grid_n, cfg.grid.grid_n))
+        for _ in range(3):
+            synim.im_apply(Fd, A, wfs, ws, out=out)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(st)
+        for _ in range(reps):
+            synim.im_apply(Fd, A, wfs, ws, out=out)
+        e1.record(st)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        print(json.dumps({"index": i, "ms": round(ms, 4),
+                          "frac": round(launch_bytes / (ms * 1e-3) / 8e12, 4),
+                          "status": synim.plan_status(ws), **c}), flush=True)
+    synim.autotune_clear()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -418,7 +460,14 @@ def main():
     ap.add_argument("--mcao-only", action="store_true",
                     help="only run the MCAO batch leg (the workload of its kernel trace) and "
                          "print its figures")
+    ap.add_argument("--schedules", type=int, nargs="?", const=-1, default=None,
+                    metavar="INDEX",
+                    help="only time the ELT stream kernel under the dynamic and the "
+                         "one-chunk-per-XCD schedules (INDEX: one entry only)")
     args = ap.parse_args()
+    if args.schedules is not None:
+        schedules_leg(args.schedules)
+        return
     if args.copy_probe:
         import torch
         src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
