@@ -36,7 +36,7 @@ def dev(x):
 def test_gemm_f64_layouts(gpu_lib):
     S = gpu_lib
     rng = np.random.default_rng(1)
-    for M, N, K in ((100, 70, 37), (64, 64, 16), (1, 130, 5), (129, 3, 200)):
+    for M, N, K in ((100, 70, 37), (64, 64, 16), (1, 130, 5), (129, 3, 200), (70, 33, 48)):
         say(f"[case] gemm {M}x{N}x{K}")
         Xk = rng.standard_normal((K, M))          # X(k, m) = Xk[k, m]: sxk = M, sxm = 1
         Yk = rng.standard_normal((N, K))          # Y(k, n) = Yk[n, k]: syk = 1, syn = K
