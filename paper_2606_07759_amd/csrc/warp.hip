@@ -7,7 +7,7 @@
 namespace synim {
 namespace {
 
-constexpr int WX = 64, WY = 16;   // one wave covers 64 consecutive output columns
+constexpr int WX = 256, WY = 4;   // four waves cover 256 consecutive output columns
 // Workgroups per launch the IF loop is split for: enough to fill 256 CUs many
 // times over, while each workgroup still reuses its FP64 source coordinates
 // over tens of IFs (16k, 32k and 128k measured within 8% of each other).
