@@ -8,6 +8,21 @@ namespace {
 constexpr int SBLOCK = 256;   // pixel columns of one workgroup
 constexpr int SROWS = 8;      // subaperture rows one workgroup walks in turn
 
+// Pixel (x, y)'s pupil-masked central differences and pupil count, added to
+// its column's sums.  The loads are unconditional (the halo keeps them in
+// bounds) so that many rows' loads can be in flight together.
+__device__ __forceinline__ void column_terms(const float* ph, const uint8_t* pupil, int W,
+                                             int Wh, int x, int y, float& gx, float& gy,
+                                             float& cnt) {
+  const bool in = pupil[(size_t)y * W + x] != 0;
+  const size_t c = (size_t)(y + 1) * Wh + (x + 1);
+  const float ex = 0.5f * (ph[c + 1] - ph[c - 1]);
+  const float ey = 0.5f * (ph[c + Wh] - ph[c - Wh]);
+  gx += in ? ex : 0.f;
+  gy += in ? ey : 0.f;
+  cnt += in ? 1.f : 0.f;
+}
+
 // One workgroup per (phase map, group of SROWS subaperture rows, run of whole
 // subapertures across SBLOCK pixel columns).  Thread t owns pixel column
 // x = x0 + t: for each subaperture row of the group it reads, row by row, the
@@ -24,7 +39,7 @@ __global__ __launch_bounds__(SBLOCK) void slopes_kernel(const float* __restrict_
                                                         int n_sub_x, int n_sub_y, int p, int nv,
                                                         int subs_per_block,
                                                         float* __restrict__ slopes) {
-  __shared__ float s_gx[SBLOCK], s_gy[SBLOCK], s_n[SBLOCK];
+  __shared__ float s_gx[2][SBLOCK], s_gy[2][SBLOCK], s_n[2][SBLOCK];
   __shared__ int s_kk[SROWS * SBLOCK];
   const int t = threadIdx.x;
   const int n_runs = (n_sub_x + subs_per_block - 1) / subs_per_block;
@@ -54,40 +69,43 @@ __global__ __launch_bounds__(SBLOCK) void slopes_kernel(const float* __restrict_
     }
     s_kk[e] = kk;
   }
-  for (int v = v0; v < v_end; ++v) {
-    float gx = 0.f, gy = 0.f, cnt = 0.f;
+  // two subaperture rows per step: twice the loads in flight between barriers
+  for (int v = v0; v < v_end; v += 2) {
+    const int nr = min(2, v_end - v);
+    float gx[2] = {0.f, 0.f}, gy[2] = {0.f, 0.f}, cnt[2] = {0.f, 0.f};
     if (t < nu * p) {
-      // loads are unconditional (the halo keeps them in bounds) so that the
-      // p rows' loads are all in flight together; the pupil selects the terms
+      if (nr == 2) {
+#pragma unroll 2
+        for (int dy = 0; dy < p; ++dy)
+#pragma unroll
+          for (int r = 0; r < 2; ++r) column_terms(ph, pupil, W, Wh, x, (v + r) * p + dy,
+                                                   gx[r], gy[r], cnt[r]);
+      } else {
 #pragma unroll 4
-      for (int dy = 0; dy < p; ++dy) {
-        const int y = v * p + dy;
-        const bool in = pupil[(size_t)y * W + x] != 0;
-        const size_t c = (size_t)(y + 1) * Wh + (x + 1);
-        const float ex = 0.5f * (ph[c + 1] - ph[c - 1]);
-        const float ey = 0.5f * (ph[c + Wh] - ph[c - Wh]);
-        gx += in ? ex : 0.f;
-        gy += in ? ey : 0.f;
-        cnt += in ? 1.f : 0.f;
+        for (int dy = 0; dy < p; ++dy)
+          column_terms(ph, pupil, W, Wh, x, v * p + dy, gx[0], gy[0], cnt[0]);
       }
     }
-    __syncthreads();   // the previous row's sums have been read (and s_kk written)
-    s_gx[t] = gx;
-    s_gy[t] = gy;
-    s_n[t] = cnt;
+    __syncthreads();   // the previous step's sums have been read (and s_kk written)
+#pragma unroll
+    for (int r = 0; r < 2; ++r) {
+      s_gx[r][t] = gx[r];
+      s_gy[r][t] = gy[r];
+      s_n[r][t] = cnt[r];
+    }
     __syncthreads();
-    if (t < nu) {
-      const int kk = s_kk[(v - v0) * nu + t];
-      if (kk >= 0) {
-        float sx = 0.f, sy = 0.f, n = 0.f;
-        for (int c = t * p; c < t * p + p; ++c) {
-          sx += s_gx[c];
-          sy += s_gy[c];
-          n += s_n[c];
-        }
-        out[kk] = n > 0.f ? sx / n : 0.f;
-        out[nv + kk] = n > 0.f ? sy / n : 0.f;
+    for (int e = t; e < nr * nu; e += SBLOCK) {
+      const int r = e / nu, u = e - r * nu;
+      const int kk = s_kk[(v - v0 + r) * nu + u];
+      if (kk < 0) continue;
+      float sx = 0.f, sy = 0.f, n = 0.f;
+      for (int c = u * p; c < u * p + p; ++c) {
+        sx += s_gx[r][c];
+        sy += s_gy[r][c];
+        n += s_n[r][c];
       }
+      out[kk] = n > 0.f ? sx / n : 0.f;
+      out[nv + kk] = n > 0.f ? sy / n : 0.f;
     }
   }
 }
