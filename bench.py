@@ -464,7 +464,22 @@ def main():
                     metavar="INDEX",
                     help="only time the ELT stream kernel under the dynamic and the "
                          "one-chunk-per-XCD schedules (INDEX: one entry only)")
+    ap.add_argument("--standalone-only", action="store_true",
+                    help="only run the standalone warp and slopes legs on the ELT stack (the "
+                         "workload of their kernel trace) and print their figures")
     args = ap.parse_args()
+    if args.standalone_only:
+        import torch
+        import paper_2606_07759_amd as synim
+        import workloads as wl
+        synim.load()
+        dev = torch.device("cuda:0")
+        cfg = wl.scao_elt(args.seed)
+        Fd = wl.if_stack_torch(cfg.grid, dev)
+        A, _ = synim.affine_from_misreg(cfg.theta, 512, 512, cfg.n_out, cfg.n_out)
+        wfs = synim.Wfs.from_numpy(cfg.pupil, cfg.p, cfg.valid, device=dev)
+        print(json.dumps(standalone_legs(synim, dev, cfg, Fd, A, wfs)), flush=True)
+        return
     if args.schedules is not None:
         schedules_leg(args.schedules)
         return
